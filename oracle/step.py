@@ -1,0 +1,196 @@
+"""One time step of the hybrid scheme (Eq. 1 with Eqs. 2-14 and the scalar update of
+Sec. 2.3), the equilibrium initialisation, field extraction and the FP64 global sums.
+
+State at level n: post-collision populations g*(n-1) (before streaming; Q x grid), the
+scalars (T, Y_1..) at level n, and the step counter n.  One step, for every cell r:
+ 1. pull g_i(r, n) = g*_i(r - c_i, n-1) with boundary substitutions (below);
+ 2. rho^n from the ideal gas; non-advective RHS R and Lambda (Eq. 3);
+ 3. P_h, u from Eq. 7;  4. grad(rho) by central differences;  5. Xi (Eq. 2);
+ 6. f' (Eq. 13);  7. collision (cumulant, Eq. 9 as read; or BGK in the same frame);
+ 8. g* (Eq. 8);  9. explicit Euler update of the scalars with u^n (Sec. 2.3);
+10. FP64 sums over fluid cells at level n.
+Solid cells keep their populations and scalars unchanged.
+
+Boundary readings (the paper names no-slip/zero-flux/adiabatic walls, an inlet and an
+exhaust without giving the methods): a link whose source r - c_i is a solid cell or
+lies beyond a wall face is bounced back halfway, g_i(r) = g*_opp(i)(r); beyond an inlet
+face it is a moving wall, g_i(r) = g*_opp(i)(r) + 2 w_i rho_in (c_i . u_w) with
+u_w = u_in (1 + a xi) and xi the counter-based noise; beyond an outlet face it is an
+anti-bounce-back pressure condition, g_i(r) = -g*_opp(i)(r) + 2 w_i [P_out +
+rho ((c_i . u_w)^2/(2 cs2) - u_w^2/2)] with rho = rho^n(r) and u_w the momentum of the
+cell's own post-collision populations.  A link leaving through several faces takes the
+first of wall, inlet, outlet.  Periodic faces wrap.
+"""
+import torch
+
+from . import cumulant, equations, noise, scalars
+from .grid import INLET, OUTLET, SOLID, Grid
+from .lattice import CS2, get as get_lattice
+
+
+def _w(lat, i):
+    return float(lat.w[i])
+
+
+def inlet_velocity(params, grid, n):
+    """u_w on every cell (only read at links that cross the inlet face)."""
+    D = grid.D
+    u_in = torch.tensor([float(v) for v in params["inlet_u"][:D]], dtype=torch.float64)
+    amp = float(params["inlet_noise"])
+    face_axis = None
+    for d in range(D):
+        if "inlet" in (params["face_bc"][2 * d], params["face_bc"][2 * d + 1]):
+            face_axis = d
+    scale = torch.ones(grid.shape, dtype=torch.float64)
+    if face_axis is not None and amp != 0.0:
+        others = [a for a in range(3) if a != face_axis]
+        coords = grid.coord + [torch.zeros_like(grid.coord[0])] * (3 - len(grid.coord))
+        a_c = coords[others[0]].numpy()
+        b_c = coords[others[1]].numpy() if len(others) > 1 else 0 * a_c
+        xi = noise.xi(params["seed"], a_c, b_c, n)
+        scale = 1.0 + amp * torch.from_numpy(xi)
+    return u_in.reshape(D, 1, 1, 1) * scale
+
+
+def pull(params, lat, grid, A, rho, n):
+    D = grid.D
+    g = torch.empty_like(A)
+    rho_in = scalars.density(params, scalars.inlet_scalars(params).reshape(-1, 1, 1, 1),
+                             (1, 1, 1)).reshape(())
+    u_in = inlet_velocity(params, grid, n)
+    u_out = torch.einsum("qd,q...->d...", lat.c, A) / (CS2 * rho)
+    uu_out = (u_out * u_out).sum(0)
+    P_out = float(params["outlet_P"])
+    for i in range(lat.Q):
+        c = [int(v) for v in lat.ci[i]]
+        offs = [-c[d] for d in range(D)] + [0] * (3 - D)
+        src = grid.shift_vec(A[i], offs)
+        solid_src = grid.shift_vec(grid.solid, offs)
+        wall = torch.zeros(grid.shape, dtype=torch.bool)
+        inl = torch.zeros_like(wall)
+        outl = torch.zeros_like(wall)
+        for d in range(D):
+            if c[d] == 0:
+                continue
+            outside, code = grid.face_of(d, -c[d])
+            wall |= outside & (code == SOLID)
+            inl |= outside & (code == INLET)
+            outl |= outside & (code == OUTLET)
+        opp = A[int(lat.opp[i])]
+        cu_in = sum(c[d] * u_in[d] for d in range(D))
+        cu_out = sum(c[d] * u_out[d] for d in range(D))
+        val_bb = opp
+        val_in = opp + 2.0 * _w(lat, i) * rho_in * cu_in
+        val_out = -opp + 2.0 * _w(lat, i) * (P_out + rho * (cu_out * cu_out / (2 * CS2) - uu_out / 2))
+        g[i] = torch.where(wall, val_bb,
+                           torch.where(inl, val_in,
+                                       torch.where(outl, val_out,
+                                                   torch.where(solid_src, val_bb, src))))
+    return g
+
+
+def _grid_of(params, solid):
+    return Grid(params, solid)
+
+
+def init_state(params, P_h, u, scal, solid=None):
+    """Populations at the equilibrium of Eq. 6 for the given fields (no non-equilibrium
+    part): g*(-1) := g_eq(P_h, rho(T, Y), u).  Fields are (nz, ny, nx) / (D, nz, ny, nx)."""
+    lat = get_lattice(params["lattice"])
+    grid = _grid_of(params, solid)
+    scal = scal.to(torch.float64) if scal is not None else torch.zeros((0,) + grid.shape,
+                                                                       dtype=torch.float64)
+    rho = scalars.density(params, scal, grid.shape)
+    A = equations.g_eq(lat, P_h.to(torch.float64), rho, u.to(torch.float64))
+    return {"pops": A, "scal": scal.clone(), "step": 0, "solid": grid.solid}
+
+
+def _level_n(params, state):
+    """Everything the step computes at level n before collision."""
+    lat = get_lattice(params["lattice"])
+    grid = _grid_of(params, state["solid"])
+    scal = state["scal"]
+    rho = scalars.density(params, scal, grid.shape)
+    g = pull(params, lat, grid, state["pops"], rho, state["step"])
+    R, Lam = scalars.nonadvective_rhs(params, grid, scal, rho)
+    P_h, u = equations.moments(lat, g, rho, Lam)
+    if params["physics"] in ("one_step", "two_step"):
+        rho_in = scalars.density(params, scalars.inlet_scalars(params).reshape(-1, 1, 1, 1),
+                                 (1, 1, 1)).reshape(())
+        grad_rho = scalars.gradient(grid, rho, float(rho_in))
+    else:
+        grad_rho = torch.zeros((grid.D,) + grid.shape, dtype=torch.float64)
+    return lat, grid, rho, g, R, Lam, P_h, u, grad_rho
+
+
+def reductions(params, grid, rho, P_h, u, scal):
+    f = grid.fluid
+    out = torch.zeros(8, dtype=torch.float64)
+    out[0] = rho[f].sum()
+    out[1] = P_h[f].sum()
+    for d in range(grid.D):
+        out[2 + d] = (rho * u[d])[f].sum()
+    out[5] = 0.5 * (rho * (u * u).sum(0))[f].sum()
+    phys = params["physics"]
+    if phys in ("isothermal", "passive"):
+        out[6] = f.sum() / float(params["T_ref"])
+    elif phys == "one_step":
+        out[6] = (1.0 / scal[0])[f].sum()
+    else:
+        out[6] = (scalars.mixture_W(params, scal[1:]) / scal[0])[f].sum()
+    if scal.shape[0] >= 2:
+        out[7] = (rho * scal[1])[f].sum()
+    return out
+
+
+def step(params, state):
+    """Advance the state by one time step; returns (new_state, sums at level n)."""
+    lat, grid, rho, g, R, Lam, P_h, u, grad_rho = _level_n(params, state)
+    Xi = equations.source_Xi(lat, rho, u, grad_rho, Lam)
+    fp = equations.precondition(g, Xi, rho)
+    nu = scalars.viscosity(params, rho)
+    if params["collision"] == "cumulant":
+        fps, _ = cumulant.cumulant_collide(lat, fp, u, nu, params["cs_smag"],
+                                           params["omega_bulk"], params["omega_high"])
+    else:
+        w = lat.w.reshape((-1,) + (1,) * 3)
+        f_t = fp - w * (fp.sum(0) - 1.0)
+        kappa = cumulant.central_moments(lat, f_t, u)
+        om = cumulant.smagorinsky_omega(lat, kappa, nu, params["cs_smag"])
+        fps = equations.bgk_preconditioned(lat, fp, P_h, rho, u, om)
+    gs = equations.post_collision(fps, Xi, rho)
+    new_scal = scalars.advance(params, grid, state["scal"], u, R)
+    solid = grid.solid
+    gs = torch.where(solid, state["pops"], gs)
+    if new_scal.shape[0]:
+        new_scal = torch.where(solid, state["scal"], new_scal)
+    sums = reductions(params, grid, rho, P_h, u, state["scal"])
+    return ({"pops": gs, "scal": new_scal, "step": state["step"] + 1,
+             "solid": state["solid"]}, sums)
+
+
+def fields(params, state):
+    """(P_h, rho, u, scalars, sums) at the state's level n."""
+    lat, grid, rho, g, R, Lam, P_h, u, grad_rho = _level_n(params, state)
+    return P_h, rho, u, state["scal"], reductions(params, grid, rho, P_h, u, state["scal"])
+
+
+def run(params, state, nsteps):
+    sums = None
+    for _ in range(nsteps):
+        state, sums = step(params, state)
+    return state, sums
+
+
+# ------------------------------------------------------------------ storage-format bridge
+def from_storage(params, ghat, P0=None):
+    """Populations from the library's storage format ghat_i = g_i/P0 - w_i (P0 = rho_ref cs2)."""
+    lat = get_lattice(params["lattice"])
+    P0 = params["rho_ref"] * CS2 if P0 is None else P0
+    return P0 * (ghat.to(torch.float64) + lat.w.reshape((-1, 1, 1, 1)))
+
+
+def to_storage(params, g):
+    lat = get_lattice(params["lattice"])
+    P0 = params["rho_ref"] * CS2
+    return g / P0 - lat.w.reshape((-1, 1, 1, 1))
