@@ -1,0 +1,144 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) hybrid low-Mach lattice-Boltzmann /
+ * finite-difference time step of Hosseini, Darabiha, Thevenin, "Low Mach number lattice
+ * Boltzmann model for turbulent combustion: flow in confined geometries"
+ * (arXiv 2207.11567).
+ *
+ * One time step (Sec. 2, Eq. 1): pull-streaming of the pressure/momentum populations g_i
+ * (D2Q9 or D3Q27, Sec. 2.1), the source term Xi_i of Eq. 2 with Lambda of Eq. 3, the
+ * moments of Eq. 7, pre-conditioning (Eq. 13), the cumulant collision in the
+ * pre-conditioned frame (Eqs. 9-12, Sec. 2.2) with a Smagorinsky shear rate, the
+ * post-collision form of Eq. 8, and the explicit-Euler finite-difference update of
+ * temperature and species (third-order WENO advection, centred diffusion, Sec. 2.3) with
+ * Arrhenius chemistry, thickened-flame scaling and ideal-gas density; bounce-back walls,
+ * a velocity inlet and a pressure outlet.  Global FP64 sums (mass, pressure, momentum,
+ * kinetic energy, thermodynamic-pressure integral) are formed every step.
+ *
+ * Conventions
+ *  - Lattice units: dr = dt = 1, cs^2 = 1/3.  P0 = rho_ref cs^2.
+ *  - Cells are ordered x fastest: n = x + nx (y + ny z); nz = 1 for D2Q9.
+ *  - Population i has velocity (cx, cy, cz) with i = (cx+1) + 3 (cy+1) + 9 (cz+1); its
+ *    opposite is Q-1-i.  Populations are stored structure-of-arrays, [Q][nz][ny][nx],
+ *    as the deviation ghat_i = g_i/P0 - w_i in the storage precision (FP64, FP32, or FP16
+ *    for LBM_FP16S).
+ *  - Scalars are stored [S][nz][ny][nx] in FP64 (LBM_FP64) or FP32 (otherwise), with
+ *    S = 0 (isothermal), 1 (passive T), 2 (T, Y_fuel), 6 (T, Y_CH4, Y_O2, Y_CO, Y_CO2,
+ *    Y_H2O; Y_N2 = 1 - sum).
+ *  - Field arrays exchanged with lbm_init_fields / lbm_fields are FP64: P_h and rho
+ *    [nz][ny][nx], u [D][nz][ny][nx], scalars [S][nz][ny][nx].
+ *  - The state at level n is (post-collision populations of level n-1, scalars at n, n).
+ *
+ * Ownership: every device buffer is allocated by the caller and passed as a device
+ * pointer; the library keeps the pointers for the solver's lifetime, never frees them and
+ * allocates no device memory of its own.  All work is queued on the caller's HIP stream;
+ * lbm_step does not synchronise, lbm_fields and the state copies do.
+ * Errors: every call returns an lbm_status; lbm_last_error gives a message.  A
+ * non-finite value produced by a step raises a device flag reported as LBM_E_DIVERGED by
+ * the next synchronising call.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_solver lbm_solver;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_INVALID = -1,     /* bad parameter, size or null pointer */
+  LBM_E_UNSUPPORTED = -2, /* valid but not built (e.g. BGK with an adjoint) */
+  LBM_E_HIP = -3,         /* a HIP runtime call failed */
+  LBM_E_DIVERGED = -4,    /* a non-finite value appeared in a step */
+  LBM_E_STATE = -5        /* call out of order (e.g. step before init) */
+} lbm_status;
+
+enum { LBM_D2Q9 = 9, LBM_D3Q27 = 27 };
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 };
+enum { LBM_CUMULANT = 0, LBM_BGK = 1 };
+enum { LBM_ISOTHERMAL = 0, LBM_PASSIVE = 1, LBM_ONE_STEP = 2, LBM_TWO_STEP = 3 };
+enum { LBM_VISC_CONST_NU = 0, LBM_VISC_CONST_MU = 1 };
+enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_INLET = 2, LBM_OUTLET = 3 };
+
+/* Problem statement (Sec. 2 and 3 of the paper), lattice units. */
+typedef struct {
+  int32_t lattice;    /* LBM_D2Q9 | LBM_D3Q27 */
+  int32_t nx, ny, nz; /* grid; nz == 1 for D2Q9 */
+  int32_t precision;  /* LBM_FP64 | LBM_FP32 | LBM_FP16S (FP16 storage, FP32 math) */
+  int32_t collision;  /* LBM_CUMULANT (Sec. 2.2) | LBM_BGK (Eq. 5, test mode) */
+  int32_t physics;    /* LBM_ISOTHERMAL | LBM_PASSIVE | LBM_ONE_STEP | LBM_TWO_STEP */
+  int32_t visc_law;   /* LBM_VISC_CONST_NU | LBM_VISC_CONST_MU (nu = nu_ref rho_ref/rho) */
+  double nu_ref;      /* kinematic viscosity at rho_ref: tau0 = nu/cs2 + 1/2 (Eq. 12) */
+  double omega_bulk;  /* rate of the second-order cumulant trace */
+  double omega_high;  /* rate of every cumulant of order >= 3 */
+  double cs_smag;     /* Smagorinsky constant (0 = off) */
+  double prandtl;     /* D = nu/Pr, unity Lewis number */
+  double thickening;  /* thickened-flame factor F: D -> F D, reaction -> reaction/F */
+  double rho_ref, T_ref;
+  int32_t face_bc[6]; /* -x,+x,-y,+y,-z,+z: LBM_PERIODIC|LBM_WALL|LBM_INLET|LBM_OUTLET */
+  double inlet_u[3];  /* inlet velocity */
+  double inlet_noise; /* relative amplitude a of u_w = u_in (1 + a xi), xi unit variance */
+  double outlet_P;    /* hydrodynamic pressure imposed at the outlet */
+  double inlet_T;     /* inlet temperature (Dirichlet) */
+  double inlet_Y[8];  /* inlet mass fractions of the transported species */
+  double weno_scale[8]; /* range R of each scalar: WENO eps = 1e-6 R^2 */
+  double chem[32];    /* LBM_ONE_STEP: B, Ta, T_u, T_ad, Y_u.
+                         LBM_TWO_STEP: B1, Ta1, B2, Ta2, c_p, W_k[6], h_k[6], W_ref. */
+  uint64_t seed;      /* counter-based inlet noise (SplitMix64) */
+} lbm_params;
+
+/* Sizes (bytes) of the caller-provided device buffers for these parameters: one
+ * population array (two are needed, A and B), one scalar array (two needed), and the
+ * work buffer (geometry words, per-block FP64 partial sums, flags).
+ * Returns LBM_E_INVALID for invalid parameters. */
+lbm_status lbm_query_sizes(const lbm_params *p, size_t *pop_bytes, size_t *scal_bytes,
+                           size_t *work_bytes);
+
+/* Validates parameters (tau0 > 1/2, F D max <= 1/(2 d) Fourier limit at rho_ref,
+ * nz == 1 for D2Q9, sizes > 0, 0 <= omegas <= 2) and binds the buffers.  stream is a
+ * hipStream_t (NULL = default stream).  scal_a/scal_b may be NULL when S == 0. */
+lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_b,
+                      void *scal_a, void *scal_b, void *work, lbm_solver **out);
+
+/* Solid cells (device uint8 [nz][ny][nx], nonzero = solid) for bounce-back walls and
+ * zero-flux scalars; NULL clears the geometry.  The mask is read once here. */
+lbm_status lbm_set_geometry(lbm_solver *s, const uint8_t *solid_dev);
+
+/* Equilibrium initialisation (Eq. 6): post-collision populations of level -1 are set to
+ * g_eq(P_h, rho(T, Y), u); scalars copied; step counter 0.  Device FP64 inputs; scal
+ * may be NULL when S == 0. */
+lbm_status lbm_init_fields(lbm_solver *s, const double *P_h, const double *u,
+                           const double *scal);
+
+/* Advances nsteps time steps (Eq. 1 + Sec. 2.3) asynchronously on the stream. */
+lbm_status lbm_step(lbm_solver *s, int32_t nsteps);
+
+/* Fields at the current level n (P_h of Eq. 7a, rho, u of Eq. 7b, scalars), each pointer
+ * may be NULL; sums_host (may be NULL) receives 8 FP64 sums over fluid cells:
+ * rho, P_h, rho u_x, rho u_y, rho u_z, rho |u|^2 / 2, W/T, rho Y_1.  Synchronises. */
+lbm_status lbm_fields(lbm_solver *s, double *P_h, double *rho, double *u, double *scal,
+                      double *sums_host);
+
+/* The 8 sums formed by the last lbm_step (at the level of its last step).  Synchronises. */
+lbm_status lbm_step_sums(lbm_solver *s, double *sums_host);
+
+/* Raw state copies (device-to-device, storage format): pops [Q][N], scal [S][N].
+ * Synchronise. */
+lbm_status lbm_get_state(lbm_solver *s, void *pops_dst, void *scal_dst, int64_t *step);
+lbm_status lbm_set_state(lbm_solver *s, const void *pops_src, const void *scal_src,
+                         int64_t step);
+
+/* Human-readable message of the last failure on this solver. */
+const char *lbm_last_error(const lbm_solver *s);
+
+void lbm_destroy(lbm_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

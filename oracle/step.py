@@ -133,7 +133,7 @@ def reductions(params, grid, rho, P_h, u, scal):
     out[5] = 0.5 * (rho * (u * u).sum(0))[f].sum()
     phys = params["physics"]
     if phys in ("isothermal", "passive"):
-        out[6] = f.sum() / float(params["T_ref"])
+        out[6] = float(f.sum()) / float(params["T_ref"])
     elif phys == "one_step":
         out[6] = (1.0 / scal[0])[f].sum()
     else:

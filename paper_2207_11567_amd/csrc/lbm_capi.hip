@@ -1,0 +1,360 @@
+// C ABI of the hybrid LB/FD time step (include/lbm.h): parameter validation, buffer
+// binding, launch sequencing on the caller's stream, and the synchronising read-backs.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/lbm.h"
+#include "lbm_launch.hpp"
+
+using namespace lbm;
+
+struct lbm_solver {
+  lbm_params p;
+  hipStream_t stream;
+  void *pop[2];
+  void *scal[2];
+  unsigned char *work;
+  int cur;
+  long long step;
+  bool initialized;
+  bool has_geom;
+  long long N;
+  int Q, NS, D, prec, nblocks;
+  int *flag;
+  double *sums;
+  double *partials;
+  void *geom;
+  std::string err;
+};
+
+static thread_local std::string g_create_err;
+
+static int n_scalars(int physics) {
+  switch (physics) {
+    case LBM_ISOTHERMAL: return 0;
+    case LBM_PASSIVE: return 1;
+    case LBM_ONE_STEP: return 2;
+    case LBM_TWO_STEP: return 6;
+  }
+  return -1;
+}
+
+static size_t pop_elem(int prec) { return prec == LBM_FP64 ? 8 : prec == LBM_FP32 ? 4 : 2; }
+static size_t scal_elem(int prec) { return prec == LBM_FP64 ? 8 : 4; }
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+  long long N;
+  int Q, NS, D, nblocks;
+  size_t pop_bytes, scal_bytes, off_flag, off_sums, off_partials, off_geom, work_bytes;
+};
+
+static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
+  char buf[256];
+  auto fail = [&](const char *m) { err = m; return LBM_E_INVALID; };
+  if (!p) return fail("params is NULL");
+  if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q27) return fail("lattice must be LBM_D2Q9 or LBM_D3Q27");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail("grid sizes must be >= 1");
+  if (p->lattice == LBM_D2Q9 && p->nz != 1) return fail("D2Q9 requires nz == 1");
+  if (p->precision < 0 || p->precision > 2) return fail("precision must be LBM_FP64, LBM_FP32 or LBM_FP16S");
+  if (p->collision != LBM_CUMULANT && p->collision != LBM_BGK) return fail("unknown collision operator");
+  const int NS = n_scalars(p->physics);
+  if (NS < 0) return fail("unknown physics");
+  if (p->visc_law != LBM_VISC_CONST_NU && p->visc_law != LBM_VISC_CONST_MU) return fail("unknown visc_law");
+  if (!(p->nu_ref > 0.0) || !isfinite(p->nu_ref)) return fail("nu_ref must be > 0 (tau0 > 1/2)");
+  if (!(p->omega_bulk >= 0.0 && p->omega_bulk <= 2.0)) return fail("omega_bulk must lie in [0, 2]");
+  if (!(p->omega_high >= 0.0 && p->omega_high <= 2.0)) return fail("omega_high must lie in [0, 2]");
+  if (!(p->cs_smag >= 0.0)) return fail("cs_smag must be >= 0");
+  if (!(p->rho_ref > 0.0) || !(p->T_ref > 0.0)) return fail("rho_ref and T_ref must be > 0");
+  if (NS > 0) {
+    if (!(p->prandtl > 0.0)) return fail("prandtl must be > 0");
+    if (!(p->thickening > 0.0)) return fail("thickening must be > 0");
+    for (int k = 0; k < NS; ++k)
+      if (!(p->weno_scale[k] > 0.0)) return fail("weno_scale must be > 0 for every scalar");
+    const double D = p->lattice == LBM_D2Q9 ? 2.0 : 3.0;
+    const double FD = p->thickening * p->nu_ref / p->prandtl;
+    if (FD > 1.0 / (2.0 * D)) {
+      snprintf(buf, sizeof buf, "explicit diffusion unstable: F nu/Pr = %g > 1/(2d) = %g", FD, 1.0 / (2.0 * D));
+      err = buf;
+      return LBM_E_INVALID;
+    }
+  }
+  if (p->physics == LBM_ONE_STEP && !(p->chem[4] > 0.0)) return fail("one-step chemistry needs Y_u > 0");
+  if (p->physics == LBM_TWO_STEP) {
+    for (int k = 5; k < 11; ++k)
+      if (!(p->chem[k] > 0.0)) return fail("two-step chemistry needs molar masses > 0");
+    if (!(p->chem[4] > 0.0) || !(p->chem[17] > 0.0)) return fail("two-step chemistry needs c_p > 0, W_ref > 0");
+  }
+  const int Dm = p->lattice == LBM_D2Q9 ? 2 : 3;
+  for (int f = 0; f < 6; ++f)
+    if (p->face_bc[f] < LBM_PERIODIC || p->face_bc[f] > LBM_OUTLET) return fail("unknown face condition");
+  for (int d = 0; d < Dm; ++d)
+    if ((p->face_bc[2 * d] == LBM_PERIODIC) != (p->face_bc[2 * d + 1] == LBM_PERIODIC))
+      return fail("periodic faces must come in pairs");
+  for (int d = 0; d < Dm; ++d)
+    for (int side = 0; side < 2; ++side)
+      if ((p->face_bc[2 * d + side] == LBM_INLET || p->face_bc[2 * d + side] == LBM_OUTLET) &&
+          (d == 0 ? p->nx : d == 1 ? p->ny : p->nz) < 3)
+        return fail("inlet/outlet axis needs at least 3 cells");
+  const long long N = (long long)p->nx * p->ny * p->nz;
+  const int Q = p->lattice;
+  if ((long long)Q * N > (1ll << 31) - 1) return fail("grid too large: Q*N must stay below 2^31");
+  L->N = N;
+  L->Q = Q;
+  L->NS = NS;
+  L->D = Dm;
+  L->nblocks = (int)((N + 255) / 256);
+  L->pop_bytes = (size_t)Q * N * pop_elem(p->precision);
+  L->scal_bytes = (size_t)NS * N * scal_elem(p->precision);
+  L->off_flag = 0;
+  L->off_sums = 64;
+  L->off_partials = 256;
+  L->off_geom = align256(L->off_partials + (size_t)L->nblocks * 8 * sizeof(double));
+  L->work_bytes = align256(L->off_geom + (size_t)N * (Q == 9 ? 4 : 8));
+  return LBM_OK;
+}
+
+static lbm_status hip_fail(lbm_solver *s, hipError_t e, const char *what) {
+  s->err = std::string(what) + ": " + hipGetErrorString(e);
+  return LBM_E_HIP;
+}
+
+static StepArgs make_args(const lbm_solver *s) {
+  const lbm_params &p = s->p;
+  StepArgs a;
+  memset(&a, 0, sizeof a);
+  a.geom = s->has_geom ? s->geom : nullptr;
+  a.partials = s->partials;
+  a.flag = s->flag;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.nz = p.nz;
+  a.N = s->N;
+  for (int f = 0; f < 6; ++f) {
+    const int c = p.face_bc[f];
+    a.face[f] = c == LBM_PERIODIC ? -1 : c == LBM_WALL ? ST_SOLID : c == LBM_INLET ? ST_INLET : ST_OUTLET;
+  }
+  if (s->D == 2) a.face[4] = a.face[5] = -1;
+  a.step = s->step;
+  a.collision = p.collision;
+  a.remap = 1;
+  a.P0 = p.rho_ref / 3.0;
+  a.wb = p.omega_bulk;
+  a.wh = p.omega_high;
+  a.smag18 = 18.0 * p.cs_smag * p.cs_smag;
+  for (int d = 0; d < 3; ++d) a.inlet_u[d] = p.inlet_u[d];
+  a.inlet_noise = p.inlet_noise;
+  a.outlet_P = p.outlet_P;
+  a.phi_in[0] = p.inlet_T;
+  for (int k = 1; k < 8; ++k) a.phi_in[k] = p.inlet_Y[k - 1];
+  for (int k = 0; k < 8; ++k) a.eps[k] = 1e-6 * p.weno_scale[k] * p.weno_scale[k];
+  a.seed = p.seed;
+  a.th.rho_ref = p.rho_ref;
+  a.th.T_ref = p.T_ref;
+  a.th.nu_ref = p.nu_ref;
+  a.th.inv_Pr = s->NS > 0 ? 1.0 / p.prandtl : 0.0;
+  a.th.F = s->NS > 0 ? p.thickening : 1.0;
+  a.th.visc_const_mu = p.visc_law == LBM_VISC_CONST_MU ? 1.0 : 0.0;
+  for (int k = 0; k < 32; ++k) a.th.chem[k] = p.chem[k];
+  return a;
+}
+
+static hipError_t launch(const lbm_solver *s, int kind, const StepArgs &a, const double *Ph = nullptr,
+                         const double *u = nullptr, const double *scal = nullptr) {
+  if (s->Q == 9) return launch_d2q9(s->prec, s->NS, kind, a, s->nblocks, s->stream, Ph, u, scal);
+  return launch_d3q27(s->prec, s->NS, kind, a, s->nblocks, s->stream, Ph, u, scal);
+}
+
+static lbm_status check_flag(lbm_solver *s) {
+  int f = 0;
+  hipError_t e = hipMemcpyAsync(&f, s->flag, sizeof(int), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "reading the divergence flag");
+  if (f & 1) {
+    s->err = "a non-finite value appeared during a time step";
+    return LBM_E_DIVERGED;
+  }
+  return LBM_OK;
+}
+
+extern "C" {
+
+lbm_status lbm_query_sizes(const lbm_params *p, size_t *pop_bytes, size_t *scal_bytes, size_t *work_bytes) {
+  Layout L;
+  lbm_status st = validate(p, &L, g_create_err);
+  if (st != LBM_OK) return st;
+  if (pop_bytes) *pop_bytes = L.pop_bytes;
+  if (scal_bytes) *scal_bytes = L.scal_bytes;
+  if (work_bytes) *work_bytes = L.work_bytes;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_b, void *scal_a, void *scal_b,
+                      void *work, lbm_solver **out) {
+  if (!out) return LBM_E_INVALID;
+  *out = nullptr;
+  Layout L;
+  lbm_status st = validate(p, &L, g_create_err);
+  if (st != LBM_OK) return st;
+  if (!pop_a || !pop_b || !work || pop_a == pop_b) {
+    g_create_err = "pop_a, pop_b (distinct) and work are required";
+    return LBM_E_INVALID;
+  }
+  if (L.NS > 0 && (!scal_a || !scal_b || scal_a == scal_b)) {
+    g_create_err = "scal_a and scal_b (distinct) are required when scalars are transported";
+    return LBM_E_INVALID;
+  }
+  lbm_solver *s = new lbm_solver();
+  s->p = *p;
+  s->stream = (hipStream_t)stream;
+  s->pop[0] = pop_a;
+  s->pop[1] = pop_b;
+  s->scal[0] = scal_a;
+  s->scal[1] = scal_b;
+  s->work = (unsigned char *)work;
+  s->cur = 0;
+  s->step = 0;
+  s->initialized = false;
+  s->has_geom = false;
+  s->N = L.N;
+  s->Q = L.Q;
+  s->NS = L.NS;
+  s->D = L.D;
+  s->prec = p->precision;
+  s->nblocks = L.nblocks;
+  s->flag = (int *)(s->work + L.off_flag);
+  s->sums = (double *)(s->work + L.off_sums);
+  s->partials = (double *)(s->work + L.off_partials);
+  s->geom = s->work + L.off_geom;
+  hipError_t e = hipMemsetAsync(s->work, 0, 256, s->stream);
+  if (e != hipSuccess) {
+    g_create_err = std::string("clearing the work buffer: ") + hipGetErrorString(e);
+    delete s;
+    return LBM_E_HIP;
+  }
+  *out = s;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_geometry(lbm_solver *s, const uint8_t *solid_dev) {
+  if (!s) return LBM_E_INVALID;
+  if (!solid_dev) {
+    s->has_geom = false;
+    return LBM_OK;
+  }
+  StepArgs a = make_args(s);
+  hipError_t e = launch_geometry(s->Q, solid_dev, s->geom, s->p.nx, s->p.ny, s->p.nz, s->N, a.face, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "geometry kernel");
+  s->has_geom = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_solver *s, const double *P_h, const double *u, const double *scal) {
+  if (!s) return LBM_E_INVALID;
+  if (!P_h || !u || (s->NS > 0 && !scal)) {
+    s->err = "P_h, u (and scal when scalars are transported) are required";
+    return LBM_E_INVALID;
+  }
+  s->step = 0;
+  StepArgs a = make_args(s);
+  a.pop_out = s->pop[s->cur];
+  a.scal_out = s->scal[s->cur];
+  hipError_t e = launch(s, LAUNCH_INIT, a, P_h, u, scal);
+  if (e != hipSuccess) return hip_fail(s, e, "init kernel");
+  e = hipMemsetAsync(s->flag, 0, sizeof(int), s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "clearing the divergence flag");
+  s->initialized = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_solver *s, int32_t nsteps) {
+  if (!s) return LBM_E_INVALID;
+  if (!s->initialized) {
+    s->err = "lbm_step before lbm_init_fields or lbm_set_state";
+    return LBM_E_STATE;
+  }
+  if (nsteps < 0) {
+    s->err = "nsteps must be >= 0";
+    return LBM_E_INVALID;
+  }
+  StepArgs a = make_args(s);
+  for (int k = 0; k < nsteps; ++k) {
+    a.pop_in = s->pop[s->cur];
+    a.pop_out = s->pop[1 - s->cur];
+    a.scal_in = s->scal[s->cur];
+    a.scal_out = s->scal[1 - s->cur];
+    a.step = s->step;
+    hipError_t e = launch(s, LAUNCH_STEP, a);
+    if (e != hipSuccess) return hip_fail(s, e, "step kernel");
+    s->cur ^= 1;
+    s->step += 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_step_sums(lbm_solver *s, double *sums_host) {
+  if (!s) return LBM_E_INVALID;
+  hipError_t e = launch_finalize(s->partials, s->nblocks, s->sums, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "finalize kernel");
+  if (sums_host) {
+    e = hipMemcpyAsync(sums_host, s->sums, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "copying sums");
+  }
+  return check_flag(s);
+}
+
+lbm_status lbm_fields(lbm_solver *s, double *P_h, double *rho, double *u, double *scal, double *sums_host) {
+  if (!s) return LBM_E_INVALID;
+  if (!s->initialized) {
+    s->err = "lbm_fields before initialisation";
+    return LBM_E_STATE;
+  }
+  StepArgs a = make_args(s);
+  a.pop_in = s->pop[s->cur];
+  a.scal_in = s->scal[s->cur];
+  a.f_P = P_h;
+  a.f_rho = rho;
+  a.f_u = u;
+  a.f_scal = scal;
+  hipError_t e = launch(s, LAUNCH_EXTRACT, a);
+  if (e != hipSuccess) return hip_fail(s, e, "field extraction kernel");
+  return lbm_step_sums(s, sums_host);
+}
+
+lbm_status lbm_get_state(lbm_solver *s, void *pops_dst, void *scal_dst, int64_t *step) {
+  if (!s) return LBM_E_INVALID;
+  const size_t pb = (size_t)s->Q * s->N * pop_elem(s->prec), sb = (size_t)s->NS * s->N * scal_elem(s->prec);
+  hipError_t e = hipSuccess;
+  if (pops_dst) e = hipMemcpyAsync(pops_dst, s->pop[s->cur], pb, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess && scal_dst && sb)
+    e = hipMemcpyAsync(scal_dst, s->scal[s->cur], sb, hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "copying the state out");
+  if (step) *step = s->step;
+  return check_flag(s);
+}
+
+lbm_status lbm_set_state(lbm_solver *s, const void *pops_src, const void *scal_src, int64_t step) {
+  if (!s) return LBM_E_INVALID;
+  if (!pops_src || (s->NS > 0 && !scal_src) || step < 0) {
+    s->err = "pops_src (and scal_src when scalars are transported) required, step >= 0";
+    return LBM_E_INVALID;
+  }
+  const size_t pb = (size_t)s->Q * s->N * pop_elem(s->prec), sb = (size_t)s->NS * s->N * scal_elem(s->prec);
+  hipError_t e = hipMemcpyAsync(s->pop[s->cur], pops_src, pb, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess && sb) e = hipMemcpyAsync(s->scal[s->cur], scal_src, sb, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->flag, 0, sizeof(int), s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "copying the state in");
+  s->step = step;
+  s->initialized = true;
+  return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_solver *s) { return s ? s->err.c_str() : g_create_err.c_str(); }
+
+void lbm_destroy(lbm_solver *s) { delete s; }
+
+}  // extern "C"

@@ -1,0 +1,31 @@
+// D2Q9 instances of the fused step (all precisions and scalar counts).
+#include "lbm_launch.hpp"
+
+namespace lbm {
+hipError_t launch_d2q9(int prec, int ns, int kind, const StepArgs &a, int nblocks, hipStream_t st,
+                       const double *Ph, const double *u, const double *scal) {
+  switch (prec) {
+    case 0: return launch_ns<9, 0>(ns, kind, a, nblocks, st, Ph, u, scal);
+    case 1: return launch_ns<9, 1>(ns, kind, a, nblocks, st, Ph, u, scal);
+    case 2: return launch_ns<9, 2>(ns, kind, a, nblocks, st, Ph, u, scal);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_geometry(int Q, const uint8_t *solid, void *geom, int nx, int ny, int nz, long long N,
+                           const int *f, hipStream_t st) {
+  const int nb = (int)((N + 255) / 256);
+  if (Q == 9)
+    hipLaunchKernelGGL(geometry_kernel<9>, dim3(nb), dim3(256), 0, st, solid, geom, nx, ny, nz, N, f[0], f[1],
+                       f[2], f[3], f[4], f[5]);
+  else
+    hipLaunchKernelGGL(geometry_kernel<27>, dim3(nb), dim3(256), 0, st, solid, geom, nx, ny, nz, N, f[0], f[1],
+                       f[2], f[3], f[4], f[5]);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_sums, dim3(1), dim3(256), 0, st, partials, nblocks, out);
+  return hipGetLastError();
+}
+}  // namespace lbm

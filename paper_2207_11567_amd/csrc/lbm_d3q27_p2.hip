@@ -1,0 +1,9 @@
+// D3Q27 instances of the fused step, precision 2 (0 FP64, 1 FP32, 2 FP16 storage).
+#include "lbm_launch.hpp"
+
+namespace lbm {
+hipError_t launch_d3q27_p2(int ns, int kind, const StepArgs &a, int nblocks, hipStream_t st,
+                            const double *Ph, const double *u, const double *scal) {
+  return launch_ns<27, 2>(ns, kind, a, nblocks, st, Ph, u, scal);
+}
+}  // namespace lbm

@@ -1,0 +1,305 @@
+// Device-side building blocks of the hybrid LB/FD time step for gfx950 (CDNA4):
+// velocity sets, storage codecs, the cumulant collision in the pre-conditioned frame,
+// and the thermochemistry / finite-difference helpers.  Everything here runs in one
+// thread per lattice cell; all loops over populations are unrolled at compile time so
+// the Q populations and their moments live in registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ------------------------------------------------------------------------ velocity sets
+// Population i has velocity (i%3-1, (i/3)%3-1, i/9-1); weights are the tensor product of
+// the 1-D third-order Gauss-Hermite weights (1/6, 2/3, 1/6) (Sec. 2.1: D2Q9, D3Q27).
+template <int Q> struct Lat;
+template <> struct Lat<9> {
+  static constexpr int D = 2;
+  static constexpr int Q = 9;
+};
+template <> struct Lat<27> {
+  static constexpr int D = 3;
+  static constexpr int Q = 27;
+};
+
+__host__ __device__ constexpr int cx(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int cy(int i) { return (i / 3) % 3 - 1; }
+__host__ __device__ constexpr int cz(int i) { return i / 9 - 1; }
+__host__ __device__ constexpr double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+template <int Q> __host__ __device__ constexpr double wgt(int i) {
+  return Q == 9 ? w1(cx(i)) * w1(cy(i)) : w1(cx(i)) * w1(cy(i)) * w1(cz(i));
+}
+// index of the link whose velocity is -e_d (its source is the +e_d neighbour)
+template <int Q> __host__ __device__ constexpr int link_from_plus(int d) {
+  return (Q - 1) / 2 - (d == 0 ? 1 : d == 1 ? 3 : 9);
+}
+template <int Q> __host__ __device__ constexpr int link_from_minus(int d) {
+  return (Q - 1) / 2 + (d == 0 ? 1 : d == 1 ? 3 : 9);
+}
+
+// ------------------------------------------------------------------------ precisions
+// PREC 0: FP64 storage and math; 1: FP32 storage and math; 2: FP16 storage, FP32 math.
+template <int PREC> struct Prec;
+template <> struct Prec<0> { using St = double; using R = double; using Sc = double; };
+template <> struct Prec<1> { using St = float; using R = float; using Sc = float; };
+template <> struct Prec<2> { using St = _Float16; using R = float; using Sc = float; };
+
+template <class R, class St> __device__ __forceinline__ R decode(St v) { return (R)v; }
+template <class St, class R> __device__ __forceinline__ St encode(R v) { return (St)v; }
+
+// status of a neighbour position for the stencils and the links
+enum : int { ST_FLUID = 0, ST_SOLID = 1, ST_INLET = 2, ST_OUTLET = 3 };
+
+// ------------------------------------------------------------------------ 1-D chimera
+// Central moments of orders 0,1,2 about u of a 3-point distribution on {-1,0,+1}
+// (Geier et al. 2015, the 1-D factor of the D2Q9/D3Q27 moment transform), in place.
+template <class R> __device__ __forceinline__ void fwd3(R &m, R &z, R &p, R u) {
+  const R k0 = m + z + p;
+  const R d = p - m;
+  const R k1 = d - u * k0;
+  const R k2 = (p + m) - R(2) * u * d + u * u * k0;
+  m = k0; z = k1; p = k2;
+}
+template <class R> __device__ __forceinline__ void inv3(R &k0, R &k1, R &k2, R u) {
+  const R a = k0, b = k1, c = k2;
+  const R uu = u * u;
+  const R zero = a * (R(1) - uu) - R(2) * u * b - c;
+  const R plus = R(0.5) * (a * (uu + u) + b * (R(2) * u + R(1)) + c);
+  const R minus = R(0.5) * (a * (uu - u) + b * (R(2) * u - R(1)) + c);
+  k0 = minus; k1 = zero; k2 = plus;
+}
+
+// ------------------------------------------------------------------------ collision
+// Cumulant collision (Sec. 2.2) on the density-one distribution f~ = w + d of the
+// pre-conditioned populations, centred on u.  d holds the deviations (sum d = 0) and is
+// replaced by the post-collision deviations.  The central moments of f~ are split into
+// the analytically known weight part kappa^w = prod_d K_{a_d}(u_d), K = (1, -u, cs2+u^2),
+// and the transformed deviation part kappa^d; second-order diagonal moments are carried
+// as A = kappa_aa - cs2 so that no O(1) quantity is ever subtracted from another.
+// Returns the shear rate used (Smagorinsky closed form on tau).
+template <class R> struct Rates {
+  R tau0;      // nu/cs2 + 1/2 (Eq. 12 read as relaxation time)
+  R smag18;    // 18 Cs^2 = 2 Cs^2 / cs2^2
+  R wb, wh;    // bulk and higher-order rates
+};
+
+template <class R>
+__device__ __forceinline__ R shear_rate(const Rates<R> &r, R PiPi) {
+  // tau = (tau0 + sqrt(tau0^2 + 2 Cs^2 Qbar / cs2^2)) / 2, Qbar = sqrt(2 Pi:Pi)
+  if (r.smag18 == R(0)) return R(1) / r.tau0;
+  const R Qbar = sqrt(R(2) * PiPi);
+  const R tau = R(0.5) * (r.tau0 + sqrt(r.tau0 * r.tau0 + r.smag18 * Qbar));
+  return R(1) / tau;
+}
+
+template <class R>
+__device__ __forceinline__ R collide_d2q9(R (&d)[9], R ux, R uy, const Rates<R> &rt) {
+  constexpr R s = R(1.0 / 3.0);
+  // forward: y sweep on lines x = 0,1,2 (stride 3), then x sweep (stride 1)
+#pragma unroll
+  for (int a = 0; a < 3; ++a) fwd3(d[a], d[a + 3], d[a + 6], uy);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) fwd3(d[3 * b], d[3 * b + 1], d[3 * b + 2], ux);
+  // kappa^d_ab at d[a + 3b]
+  const R ux2 = ux * ux, uy2 = uy * uy;
+  const R A = ux2 + d[2], B = uy2 + d[6];
+  const R k11 = ux * uy + d[4];
+  const R k21 = d[5] - (s + ux2) * uy;
+  const R k12 = d[7] - ux * (s + uy2);
+  const R c22 = d[8] - s * (d[2] + d[6]) + ux2 * uy2 - A * B - R(2) * k11 * k11;
+  const R om = shear_rate(rt, A * A + B * B + R(2) * k11 * k11);
+  // relax
+  const R Dxy = (R(1) - om) * (A - B);
+  const R Tr = (R(1) - rt.wb) * (A + B);
+  const R As = R(0.5) * (Tr + Dxy), Bs = R(0.5) * (Tr - Dxy);
+  const R k11s = (R(1) - om) * k11;
+  const R h = R(1) - rt.wh;
+  const R c21s = h * k21, c12s = h * k12, c22s = h * c22;
+  // back to deviation moments (orders 0 and 1 pass through)
+  d[2] = As - ux2;
+  d[6] = Bs - uy2;
+  d[4] = k11s - ux * uy;
+  d[5] = c21s + (s + ux2) * uy;
+  d[7] = c12s + ux * (s + uy2);
+  d[8] = c22s + s * (As - ux2 + Bs - uy2) + As * Bs - ux2 * uy2 + R(2) * k11s * k11s;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) inv3(d[3 * b], d[3 * b + 1], d[3 * b + 2], ux);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) inv3(d[a], d[a + 3], d[a + 6], uy);
+  return om;
+}
+
+template <class R>
+__device__ __forceinline__ R collide_d3q27(R (&d)[27], R ux, R uy, R uz, const Rates<R> &rt) {
+  constexpr R s = R(1.0 / 3.0);
+  // forward sweeps z (stride 9), y (stride 3), x (stride 1); kappa^d_abc at d[a+3b+9c]
+#pragma unroll
+  for (int j = 0; j < 9; ++j) fwd3(d[j], d[j + 9], d[j + 18], uz);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fwd3(d[a + 9 * c], d[a + 3 + 9 * c], d[a + 6 + 9 * c], uy);
+#pragma unroll
+  for (int j = 0; j < 9; ++j) fwd3(d[3 * j], d[3 * j + 1], d[3 * j + 2], ux);
+
+#define KD(a, b, c) d[(a) + 3 * (b) + 9 * (c)]
+  const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+  const R Kx2 = s + ux2, Ky2 = s + uy2, Kz2 = s + uz2;
+  // second order (diagonal shifted by cs2)
+  const R A = ux2 + KD(2, 0, 0), B = uy2 + KD(0, 2, 0), C = uz2 + KD(0, 0, 2);
+  const R k110 = ux * uy + KD(1, 1, 0), k101 = ux * uz + KD(1, 0, 1), k011 = uy * uz + KD(0, 1, 1);
+  // third order: kappa = kappa^w + kappa^d
+  const R k210 = KD(2, 1, 0) - Kx2 * uy, k201 = KD(2, 0, 1) - Kx2 * uz;
+  const R k120 = KD(1, 2, 0) - ux * Ky2, k021 = KD(0, 2, 1) - Ky2 * uz;
+  const R k102 = KD(1, 0, 2) - ux * Kz2, k012 = KD(0, 1, 2) - uy * Kz2;
+  const R k111 = KD(1, 1, 1) - ux * uy * uz;
+  // fourth order cumulants
+  const R c211 = KD(2, 1, 1) - s * KD(0, 1, 1) + ux2 * uy * uz - A * k011 - R(2) * k110 * k101;
+  const R c121 = KD(1, 2, 1) - s * KD(1, 0, 1) + uy2 * ux * uz - B * k101 - R(2) * k110 * k011;
+  const R c112 = KD(1, 1, 2) - s * KD(1, 1, 0) + uz2 * ux * uy - C * k110 - R(2) * k101 * k011;
+  const R c220 = KD(2, 2, 0) - s * (KD(2, 0, 0) + KD(0, 2, 0)) + ux2 * uy2 - A * B - R(2) * k110 * k110;
+  const R c202 = KD(2, 0, 2) - s * (KD(2, 0, 0) + KD(0, 0, 2)) + ux2 * uz2 - A * C - R(2) * k101 * k101;
+  const R c022 = KD(0, 2, 2) - s * (KD(0, 2, 0) + KD(0, 0, 2)) + uy2 * uz2 - B * C - R(2) * k011 * k011;
+  // fifth order cumulants
+  const R s2 = s * s;
+  const R c221 = KD(2, 2, 1) + uz * (s2 - ux2 * uy2) - s * (KD(0, 2, 1) + KD(2, 0, 1)) - A * k021 -
+                 B * k201 - R(4) * k110 * k111 - R(2) * (k101 * k120 + k011 * k210);
+  const R c212 = KD(2, 1, 2) + uy * (s2 - ux2 * uz2) - s * (KD(0, 1, 2) + KD(2, 1, 0)) - A * k012 -
+                 C * k210 - R(4) * k101 * k111 - R(2) * (k110 * k102 + k011 * k201);
+  const R c122 = KD(1, 2, 2) + ux * (s2 - uy2 * uz2) - s * (KD(1, 0, 2) + KD(1, 2, 0)) - B * k102 -
+                 C * k120 - R(4) * k011 * k111 - R(2) * (k110 * k012 + k101 * k021);
+  // sixth order cumulant
+  const R c222 = KD(2, 2, 2) - s2 * (KD(2, 0, 0) + KD(0, 2, 0) + KD(0, 0, 2)) +
+                 s * (ux2 * uy2 + uy2 * uz2 + uz2 * ux2 - A * B - B * C - C * A) +
+                 ux2 * uy2 * uz2 - A * B * C - (s + A) * c022 - (s + B) * c202 - (s + C) * c220 -
+                 R(4) * (k110 * c112 + k101 * c121 + k011 * c211) - R(4) * k111 * k111 -
+                 R(2) * (k210 * k012 + k201 * k021 + k120 * k102) -
+                 R(2) * ((s + A) * k011 * k011 + (s + B) * k101 * k101 + (s + C) * k110 * k110) -
+                 R(8) * k110 * k101 * k011;
+
+  const R om = shear_rate(rt, A * A + B * B + C * C + R(2) * (k110 * k110 + k101 * k101 + k011 * k011));
+  // relaxation towards the cumulant equilibria
+  const R o1 = R(1) - om, h = R(1) - rt.wh;
+  const R Dxy = o1 * (A - B), Dxz = o1 * (A - C);
+  const R Tr = (R(1) - rt.wb) * (A + B + C);
+  const R As = (Tr + Dxy + Dxz) * R(1.0 / 3.0);
+  const R Bs = As - Dxy, Cs = As - Dxz;
+  const R q110 = o1 * k110, q101 = o1 * k101, q011 = o1 * k011;
+  const R q210 = h * k210, q201 = h * k201, q120 = h * k120, q021 = h * k021, q102 = h * k102,
+          q012 = h * k012, q111 = h * k111;
+  const R q211 = h * c211, q121 = h * c121, q112 = h * c112, q220 = h * c220, q202 = h * c202,
+          q022 = h * c022;
+  const R q221 = h * c221, q212 = h * c212, q122 = h * c122, q222 = h * c222;
+
+  // back to deviation central moments: kappa*^d = kappa* - kappa^w
+  KD(2, 0, 0) = As - ux2;
+  KD(0, 2, 0) = Bs - uy2;
+  KD(0, 0, 2) = Cs - uz2;
+  KD(1, 1, 0) = q110 - ux * uy;
+  KD(1, 0, 1) = q101 - ux * uz;
+  KD(0, 1, 1) = q011 - uy * uz;
+  KD(2, 1, 0) = q210 + Kx2 * uy;
+  KD(2, 0, 1) = q201 + Kx2 * uz;
+  KD(1, 2, 0) = q120 + ux * Ky2;
+  KD(0, 2, 1) = q021 + Ky2 * uz;
+  KD(1, 0, 2) = q102 + ux * Kz2;
+  KD(0, 1, 2) = q012 + uy * Kz2;
+  KD(1, 1, 1) = q111 + ux * uy * uz;
+  KD(2, 1, 1) = q211 + s * (q011 - uy * uz) + As * q011 - ux2 * uy * uz + R(2) * q110 * q101;
+  KD(1, 2, 1) = q121 + s * (q101 - ux * uz) + Bs * q101 - uy2 * ux * uz + R(2) * q110 * q011;
+  KD(1, 1, 2) = q112 + s * (q110 - ux * uy) + Cs * q110 - uz2 * ux * uy + R(2) * q101 * q011;
+  KD(2, 2, 0) = q220 + s * (As - ux2 + Bs - uy2) + As * Bs - ux2 * uy2 + R(2) * q110 * q110;
+  KD(2, 0, 2) = q202 + s * (As - ux2 + Cs - uz2) + As * Cs - ux2 * uz2 + R(2) * q101 * q101;
+  KD(0, 2, 2) = q022 + s * (Bs - uy2 + Cs - uz2) + Bs * Cs - uy2 * uz2 + R(2) * q011 * q011;
+  KD(2, 2, 1) = q221 + (s + As) * q021 + (s + Bs) * q201 + R(4) * q110 * q111 +
+                R(2) * (q101 * q120 + q011 * q210) + uz * Kx2 * Ky2;
+  KD(2, 1, 2) = q212 + (s + As) * q012 + (s + Cs) * q210 + R(4) * q101 * q111 +
+                R(2) * (q110 * q102 + q011 * q201) + uy * Kx2 * Kz2;
+  KD(1, 2, 2) = q122 + (s + Bs) * q102 + (s + Cs) * q120 + R(4) * q011 * q111 +
+                R(2) * (q110 * q012 + q101 * q021) + ux * Ky2 * Kz2;
+  KD(2, 2, 2) = q222 + s2 * (As - ux2 + Bs - uy2 + Cs - uz2) +
+                s * (As * Bs + Bs * Cs + Cs * As - ux2 * uy2 - uy2 * uz2 - uz2 * ux2) +
+                As * Bs * Cs - ux2 * uy2 * uz2 + (s + As) * q022 + (s + Bs) * q202 + (s + Cs) * q220 +
+                R(4) * (q110 * q112 + q101 * q121 + q011 * q211) + R(4) * q111 * q111 +
+                R(2) * (q210 * q012 + q201 * q021 + q120 * q102) +
+                R(2) * ((s + As) * q011 * q011 + (s + Bs) * q101 * q101 + (s + Cs) * q110 * q110) +
+                R(8) * q110 * q101 * q011;
+#undef KD
+  // inverse sweeps x, y, z
+#pragma unroll
+  for (int j = 0; j < 9; ++j) inv3(d[3 * j], d[3 * j + 1], d[3 * j + 2], ux);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) inv3(d[a + 9 * c], d[a + 3 + 9 * c], d[a + 6 + 9 * c], uy);
+#pragma unroll
+  for (int j = 0; j < 9; ++j) inv3(d[j], d[j + 9], d[j + 18], uz);
+  return om;
+}
+
+// Second central moments of the deviation (for the BGK test mode's shear rate).
+template <int Q, class R>
+__device__ __forceinline__ R pipi_of(const R (&d)[Q], const R (&u)[3]) {
+  constexpr int D = Lat<Q>::D;
+  R P[3][3];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) P[a][b] = u[a] * u[b];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R c[3] = {R(cx(i)) - u[0], R(cy(i)) - u[1], R(Q == 27 ? cz(i) : 0) - u[2]};
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) P[a][b] += c[a] * c[b] * d[i];
+  }
+  R s = R(0);
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) s += P[a][b] * P[a][b];
+  return s;
+}
+
+// ------------------------------------------------------------------------ scalars
+// Physics selected by the number of transported scalars: 0 isothermal, 1 passive
+// temperature, 2 (T, Y_fuel) one-step, 6 (T, CH4, O2, CO, CO2, H2O) two-step.
+struct Thermo {
+  double rho_ref, T_ref, nu_ref, inv_Pr, F, visc_const_mu;
+  double chem[32];
+};
+
+template <int NS, class R>
+__device__ __forceinline__ R density(const Thermo &t, const R (&v)[NS > 0 ? NS : 1]) {
+  if constexpr (NS <= 1) {
+    return R(t.rho_ref);
+  } else if constexpr (NS == 2) {
+    return R(t.rho_ref * t.T_ref) / v[0];
+  } else {
+    // rho = rho_ref (T_ref/T)(W/W_ref), 1/W = sum Y_k/W_k with N2 by closure
+    R ysum = R(0), inv = R(0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      ysum += v[1 + k];
+      inv += v[1 + k] * R(1.0 / t.chem[5 + k]);
+    }
+    inv += (R(1) - ysum) * R(1.0 / t.chem[10]);
+    return R(t.rho_ref * t.T_ref / t.chem[17]) / (v[0] * inv);
+  }
+}
+
+template <class R> __device__ __forceinline__ R viscosity(const Thermo &t, R rho) {
+  return t.visc_const_mu != 0.0 ? R(t.nu_ref * t.rho_ref) / rho : R(t.nu_ref);
+}
+
+// Jiang-Shu WENO3 face value between b and c from the upwind-biased triple (a, b, c).
+template <class R> __device__ __forceinline__ R weno3_face(R a, R b, R c, R eps) {
+  const R b0 = (b - a) * (b - a), b1 = (c - b) * (c - b);
+  const R e0 = eps + b0, e1 = eps + b1;
+  const R a0 = R(1.0 / 3.0) * e1 * e1, a1 = R(2.0 / 3.0) * e0 * e0;   // alpha ratios
+  return (a0 * (R(-0.5) * a + R(1.5) * b) + a1 * (R(0.5) * b + R(0.5) * c)) / (a0 + a1);
+}
+
+}  // namespace lbm

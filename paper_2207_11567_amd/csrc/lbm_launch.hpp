@@ -1,0 +1,44 @@
+// Host-side launch entry points of the step kernels, one set per (lattice, precision,
+// scalar count) instance; defined in the per-lattice translation units.
+#pragma once
+
+#include "lbm_step.hpp"
+
+namespace lbm {
+
+enum LaunchKind { LAUNCH_STEP = 0, LAUNCH_EXTRACT = 1, LAUNCH_INIT = 2 };
+
+// Returns hipSuccess or the launch error.  nblocks covers N cells with 256 threads.
+hipError_t launch_d2q9(int prec, int ns, int kind, const StepArgs &a, int nblocks, hipStream_t st,
+                       const double *Ph, const double *u, const double *scal);
+hipError_t launch_d3q27(int prec, int ns, int kind, const StepArgs &a, int nblocks, hipStream_t st,
+                        const double *Ph, const double *u, const double *scal);
+hipError_t launch_geometry(int Q, const uint8_t *solid, void *geom, int nx, int ny, int nz, long long N,
+                           const int *face, hipStream_t st);
+hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t st);
+
+template <int Q, int PREC, int NS>
+hipError_t launch_one(int kind, const StepArgs &a, int nblocks, hipStream_t st, const double *Ph,
+                      const double *u, const double *scal) {
+  if (kind == LAUNCH_STEP)
+    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false>), dim3(nblocks), dim3(256), 0, st, a);
+  else if (kind == LAUNCH_EXTRACT)
+    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true>), dim3(nblocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((init_kernel<Q, PREC, NS>), dim3(nblocks), dim3(256), 0, st, a, Ph, u, scal);
+  return hipGetLastError();
+}
+
+template <int Q, int PREC>
+hipError_t launch_ns(int ns, int kind, const StepArgs &a, int nblocks, hipStream_t st, const double *Ph,
+                     const double *u, const double *scal) {
+  switch (ns) {
+    case 0: return launch_one<Q, PREC, 0>(kind, a, nblocks, st, Ph, u, scal);
+    case 1: return launch_one<Q, PREC, 1>(kind, a, nblocks, st, Ph, u, scal);
+    case 2: return launch_one<Q, PREC, 2>(kind, a, nblocks, st, Ph, u, scal);
+    case 6: return launch_one<Q, PREC, 6>(kind, a, nblocks, st, Ph, u, scal);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

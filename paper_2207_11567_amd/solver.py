@@ -1,0 +1,117 @@
+"""Python face of the HIP library: torch supplies device memory and the stream; every
+step of the time-step path runs in the library's kernels (include/lbm.h)."""
+import ctypes
+
+import torch
+
+from . import _capi as C
+
+STORAGE_DTYPE = {"fp64": torch.float64, "fp32": torch.float32, "fp16s": torch.float16}
+SCALAR_DTYPE = {"fp64": torch.float64, "fp32": torch.float32, "fp16s": torch.float32}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Solver:
+    """One lattice (D2Q9 or D3Q27) with its A/B population and scalar buffers on a GPU."""
+
+    def __init__(self, params, device="cuda", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU; none is visible")
+        self.params = dict(params)
+        self.device = torch.device(device)
+        self._p = C.make_params(self.params)
+        lib = C.lib()
+        pb, sb, wb = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        C.check(lib.lbm_query_sizes(ctypes.byref(self._p), ctypes.byref(pb), ctypes.byref(sb),
+                                    ctypes.byref(wb)))
+        self.Q = C.LATTICE[self.params["lattice"]]
+        self.D = 2 if self.Q == 9 else 3
+        self.NS = C.N_SCALARS[self.params["physics"]]
+        self.shape = (self.params["nz"], self.params["ny"], self.params["nx"])
+        self.N = self.shape[0] * self.shape[1] * self.shape[2]
+        prec = self.params["precision"]
+        self.pop_dtype = STORAGE_DTYPE[prec]
+        self.scal_dtype = SCALAR_DTYPE[prec]
+        dev = self.device
+        with torch.cuda.device(dev):
+            self.pop = [torch.empty(pb.value, dtype=torch.uint8, device=dev) for _ in range(2)]
+            self.scal = [torch.empty(max(sb.value, 1), dtype=torch.uint8, device=dev) for _ in range(2)]
+            self.work = torch.zeros(wb.value, dtype=torch.uint8, device=dev)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        C.check(lib.lbm_create(ctypes.byref(self._p), ctypes.c_void_p(self.stream.cuda_stream),
+                               _ptr(self.pop[0]), _ptr(self.pop[1]),
+                               _ptr(self.scal[0]) if self.NS else None,
+                               _ptr(self.scal[1]) if self.NS else None,
+                               _ptr(self.work), ctypes.byref(h)))
+        self._h = h
+        self._mask = None
+
+    # ---------------------------------------------------------------- lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            C.lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, status):
+        C.check(status, self._h)
+
+    def _dev(self, a, dtype=torch.float64):
+        t = torch.as_tensor(a, dtype=dtype)
+        return t.to(self.device).contiguous()
+
+    # ---------------------------------------------------------------- API
+    def set_geometry(self, solid):
+        if solid is None:
+            self._chk(C.lib().lbm_set_geometry(self._h, None))
+            return
+        self._mask = self._dev(solid, torch.uint8).reshape(self.shape)
+        self._chk(C.lib().lbm_set_geometry(self._h, _ptr(self._mask)))
+
+    def init_fields(self, P_h, u, scal=None):
+        P = self._dev(P_h).reshape(self.shape)
+        U = self._dev(u).reshape((self.D,) + self.shape)
+        S = self._dev(scal).reshape((self.NS,) + self.shape) if self.NS else None
+        self._chk(C.lib().lbm_init_fields(self._h, _ptr(P), _ptr(U), _ptr(S)))
+        torch.cuda.synchronize(self.device)
+
+    def step(self, n=1):
+        self._chk(C.lib().lbm_step(self._h, int(n)))
+
+    def fields(self):
+        dev = self.device
+        P = torch.empty(self.shape, dtype=torch.float64, device=dev)
+        rho = torch.empty_like(P)
+        u = torch.empty((self.D,) + self.shape, dtype=torch.float64, device=dev)
+        S = torch.empty((max(self.NS, 1),) + self.shape, dtype=torch.float64, device=dev)
+        sums = (ctypes.c_double * 8)()
+        self._chk(C.lib().lbm_fields(self._h, _ptr(P), _ptr(rho), _ptr(u),
+                                     _ptr(S) if self.NS else None, sums))
+        return {"P_h": P, "rho": rho, "u": u, "scal": S[:self.NS], "sums": list(sums)}
+
+    def step_sums(self):
+        sums = (ctypes.c_double * 8)()
+        self._chk(C.lib().lbm_step_sums(self._h, sums))
+        return list(sums)
+
+    def get_state(self):
+        pops = torch.empty((self.Q,) + self.shape, dtype=self.pop_dtype, device=self.device)
+        scal = torch.empty((self.NS,) + self.shape, dtype=self.scal_dtype, device=self.device)
+        step = ctypes.c_int64()
+        self._chk(C.lib().lbm_get_state(self._h, _ptr(pops), _ptr(scal) if self.NS else None,
+                                        ctypes.byref(step)))
+        return pops, scal, step.value
+
+    def set_state(self, pops, scal=None, step=0):
+        P = self._dev(pops, self.pop_dtype).reshape((self.Q,) + self.shape)
+        S = self._dev(scal, self.scal_dtype).reshape((self.NS,) + self.shape) if self.NS else None
+        self._chk(C.lib().lbm_set_state(self._h, _ptr(P), _ptr(S), int(step)))
