@@ -1,0 +1,280 @@
+"""Throughput of the hybrid low-Mach LB/FD time step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload reacting_box] [--no-cpu]
+                [--no-extra] [--kernel-only]
+
+Prints one JSON line.  A step is one pass of the whole hot path over the grid: pull
+streaming with boundary conditions, scalar stencils and chemistry, moments, source,
+cumulant collision, the finite-difference scalar update and the FP64 block sums.
+value = lattice updates per second (MLUPS) with every buffer resident in HBM; timed with
+HIP events on the stream the kernels run on.  The roofline figure uses the algorithmic
+bytes of one launch (2 Q s_pop + 2 S s_scal + geometry word + block partials, per cell)
+over the average launch duration.  The CPU baseline times the FP64 oracle on a bounded
+sample of the same workload on the host cores.
+"""
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import lbm_inputs as L  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+CS2 = 1.0 / 3.0
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2207_11567_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# ------------------------------------------------------------------------ workloads
+def workload(name, precision=None):
+    """(params, P_h, u, scal or None, solid mask or None, description)."""
+    if name == "reacting_box":
+        p, P, u, s = L.reacting_box()
+        desc = "reacting box 192x192x384 D3Q27 FP32, 2-step CH4/air (6 scalars), F=5, inlet/outlet z"
+        solid = None
+    elif name == "flame2d":
+        p, P, u, s, solid = L.flame2d()
+        desc = "2-D flame 1024x256 D2Q9, 1-step Arrhenius, F=4, 3 obstacles, walls + outlet"
+    elif name == "hit":
+        p, P, u = L.hit(256)
+        s, solid = None, None
+        desc = "decaying isotropic turbulence 256^3 D3Q27, Smagorinsky 0.17"
+    elif name == "tgv":
+        p, P, u = L.tgv(128)
+        s, solid = None, None
+        desc = "Taylor-Green vortex 128^2 D2Q9"
+    elif name == "passive_box":
+        p, P, u = L.hit(128, seed=11567)
+        s = L.passive_field(128)[None]
+        p.update(physics="passive", prandtl=0.7, weno_scale=[1.0] * 8, precision="fp32")
+        solid = None
+        desc = "HIT 128^3 D3Q27 FP32 with a passive temperature"
+    else:
+        raise ValueError(name)
+    if precision is not None:
+        p["precision"] = precision
+    return p, P, u, s, solid, desc
+
+
+def bytes_per_cell(p):
+    Q = 9 if p["lattice"] == "D2Q9" else 27
+    NS = {"isothermal": 0, "passive": 1, "one_step": 2, "two_step": 6}[p["physics"]]
+    sp = {"fp64": 8, "fp32": 4, "fp16s": 2}[p["precision"]]
+    ss = 8 if p["precision"] == "fp64" else 4
+    return 2 * Q * sp + 2 * NS * ss + 64.0 / 256.0
+
+
+def run_gpu(name, steps, warmup, precision=None):
+    import torch
+
+    from paper_2207_11567_amd import Solver
+    p, P, u, s, solid, desc = workload(name, precision)
+    solver = Solver(p, device="cuda:0")
+    if solid is not None:
+        solver.set_geometry(torch.from_numpy(solid))
+    solver.init_fields(torch.from_numpy(P), torch.from_numpy(u),
+                       torch.from_numpy(s) if s is not None else None)
+    del P, u, s
+    N = p["nx"] * p["ny"] * p["nz"]
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(solver.stream)
+    solver.step(steps)
+    e1.record(solver.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sums = solver.step_sums()            # raises on a non-finite value
+    bpc = bytes_per_cell(p) + (4 if (solid is not None and p["lattice"] == "D2Q9") else 0) \
+        + (8 if (solid is not None and p["lattice"] == "D3Q27") else 0)
+    t_launch = ms / 1e3 / steps
+    achieved = bpc * N / t_launch / 1e9
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    return {"workload": name, "desc": desc, "params": p, "cells": N, "steps": steps,
+            "ms_per_step": ms / steps, "mlups": N * steps / (ms / 1e3) / 1e6,
+            "bytes_per_cell": bpc, "achieved_gbs": achieved, "sums": sums}
+
+
+def cpu_baseline(name, budget_s=15.0):
+    """The FP64 oracle as it stands, on a bounded sample of the workload."""
+    import torch
+
+    from oracle import step as OS
+    if name == "reacting_box":
+        p, P, u, s = L.reacting_box(32, 32, 64)
+        solid = None
+        sample = "reacting box 32x32x64 copy (same physics), oracle steps until the time budget"
+    elif name == "flame2d":
+        p, P, u, s, solid = L.flame2d(256, 64)
+        sample = "2-D flame 256x64 copy"
+    elif name == "hit":
+        p, P, u = L.hit(48)
+        s, solid = None, None
+        sample = "HIT 48^3 copy"
+    else:
+        p, P, u = L.tgv(128)
+        s, solid = None, None
+        sample = "TGV 128^2"
+    st = OS.init_state(p, torch.from_numpy(P), torch.from_numpy(u),
+                       torch.from_numpy(s) if s is not None else None,
+                       torch.from_numpy(solid).bool() if solid is not None else None)
+    N = p["nx"] * p["ny"] * p["nz"]
+    OS.step(p, st)
+    t0 = time.time()
+    n = 0
+    while n < 2 or time.time() - t0 < budget_s:
+        st, _ = OS.step(p, st)
+        n += 1
+        if n >= 200:
+            break
+    dt = time.time() - t0
+    return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle", "sample": f"{sample}: {N} cells x {n} steps in {dt:.1f} s (FP64)"}
+
+
+def traffic_for(name, p, bpc, N):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on
+    the current kernel sources."""
+    f = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def precision_errors(steps=200, n=64):
+    """FP32 and FP16-storage runs against the FP64 run of the same seeded HIT field
+    (velocity relative L2 error and shell-averaged energy-spectrum error)."""
+    import torch
+
+    from paper_2207_11567_amd import Solver
+    p0, P, u = L.hit(n)
+    out = {}
+    fields = {}
+    for prec in ("fp64", "fp32", "fp16s"):
+        p = dict(p0, precision=prec)
+        s = Solver(p, device="cuda:0")
+        s.init_fields(torch.from_numpy(P), torch.from_numpy(u))
+        s.step(steps)
+        fields[prec] = s.fields()["u"].cpu().numpy()
+        s.close()
+
+    def spectrum(v):
+        vk = np.fft.fftn(v, axes=(1, 2, 3))
+        e = 0.5 * (np.abs(vk) ** 2).sum(0)
+        k = np.fft.fftfreq(n) * n
+        K = np.sqrt(k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2)
+        shells = np.rint(K).astype(int)
+        return np.bincount(shells.ravel(), e.ravel())[1:n // 2]
+
+    ref = fields["fp64"]
+    Eref = spectrum(ref)
+    for prec in ("fp32", "fp16s"):
+        d = fields[prec] - ref
+        E = spectrum(fields[prec])
+        out[prec] = {"u_rel_l2": float(np.sqrt((d ** 2).sum() / (ref ** 2).sum())),
+                     "spectrum_max_rel_err": float(np.max(np.abs(E - Eref) / Eref)),
+                     "case": f"HIT {n}^3, {steps} steps"}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="reacting_box",
+                    choices=["reacting_box", "flame2d", "hit", "tgv", "passive_box"])
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "fp16s"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="time the main workload only (for profiler runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run a plain 1 GiB device copy 3 times (counter calibration) and exit")
+    args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4,
+                          "launches": 3}))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the time step is measured on one "
+                                   "MI355X; multi-GPU sharding is a design note only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    main_res = run_gpu(args.workload, args.steps, args.warmup, args.precision)
+    p = main_res["params"]
+    N = main_res["cells"]
+    print(f"# {args.workload}: {main_res['mlups']:.1f} MLUPS, {main_res['ms_per_step']:.3f} ms/step",
+          file=sys.stderr, flush=True)
+    if args.kernel_only:
+        return
+    traffic = traffic_for(args.workload, p, main_res["bytes_per_cell"], N)
+    achieved = main_res["achieved_gbs"]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": main_res["bytes_per_cell"] * N}
+    extra = {}
+    if not args.no_extra:
+        for name, prec, k in (("tgv", "fp64", 1000), ("flame2d", "fp64", 400),
+                              ("flame2d", "fp32", 400), ("hit", "fp64", 40), ("hit", "fp32", 60),
+                              ("hit", "fp16s", 60), ("passive_box", "fp32", 100)):
+            r = run_gpu(name, k, 10, prec)
+            extra[f"{name}_{prec}"] = {"mlups": round(r["mlups"], 1),
+                                       "ms_per_step": round(r["ms_per_step"], 4),
+                                       "achieved_gbs": round(r["achieved_gbs"], 1),
+                                       "hbm_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                                       "cells": r["cells"], "desc": r["desc"]}
+            print(f"# {name} {prec}: {r['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
+        extra["precision_error_vs_fp64"] = precision_errors()
+    cpu = None if args.no_cpu else cpu_baseline(args.workload)
+    line = {
+        "metric": "MLUPS of full hybrid step, % HBM roofline; FP16/32 vs FP64 error; adjoint/fwd",
+        "value": round(main_res["mlups"], 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32",
+                                                          "fp16s": "f16-storage/f32"}[p["precision"]],
+        "data": "synthetic (seeded)",
+        "config": {"workload": main_res["desc"], "nx": p["nx"], "ny": p["ny"], "nz": p["nz"],
+                   "lattice": p["lattice"], "precision": p["precision"], "physics": p["physics"],
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu,
+        "paper_context": {"value": 0.4, "unit": "MLUPS", "hardware": "SuperMUC-NG CPU cluster",
+                          "note": "LB + FD + thermochemistry on PRECCINSTA (about 30 Mi points); "
+                                  "not a target"},
+        "extra": extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
