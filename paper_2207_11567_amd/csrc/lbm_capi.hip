@@ -26,6 +26,7 @@ struct lbm_solver {
   int *flag;
   double *sums;
   double *partials;
+  double *stage;
   void *geom;
   std::string err;
 };
@@ -49,7 +50,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   long long N;
   int Q, NS, D, nblocks;
-  size_t pop_bytes, scal_bytes, off_flag, off_sums, off_partials, off_geom, work_bytes;
+  size_t pop_bytes, scal_bytes, off_flag, off_sums, off_stage, off_partials, off_geom, work_bytes;
 };
 
 static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
@@ -111,7 +112,8 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   L->scal_bytes = (size_t)NS * N * scal_elem(p->precision);
   L->off_flag = 0;
   L->off_sums = 64;
-  L->off_partials = 256;
+  L->off_stage = 256;
+  L->off_partials = L->off_stage + 256 * 8 * sizeof(double);
   L->off_geom = align256(L->off_partials + (size_t)L->nblocks * 8 * sizeof(double));
   L->work_bytes = align256(L->off_geom + (size_t)N * (Q == 9 ? 4 : 8));
   return LBM_OK;
@@ -228,6 +230,7 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
   s->flag = (int *)(s->work + L.off_flag);
   s->sums = (double *)(s->work + L.off_sums);
   s->partials = (double *)(s->work + L.off_partials);
+  s->stage = (double *)(s->work + L.off_stage);
   s->geom = s->work + L.off_geom;
   hipError_t e = hipMemsetAsync(s->work, 0, 256, s->stream);
   if (e != hipSuccess) {
@@ -297,7 +300,7 @@ lbm_status lbm_step(lbm_solver *s, int32_t nsteps) {
 
 lbm_status lbm_step_sums(lbm_solver *s, double *sums_host) {
   if (!s) return LBM_E_INVALID;
-  hipError_t e = launch_finalize(s->partials, s->nblocks, s->sums, s->stream);
+  hipError_t e = launch_finalize(s->partials, s->nblocks, s->stage, s->sums, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "finalize kernel");
   if (sums_host) {
     e = hipMemcpyAsync(sums_host, s->sums, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream);

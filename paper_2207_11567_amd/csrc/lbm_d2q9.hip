@@ -24,8 +24,11 @@ hipError_t launch_geometry(int Q, const uint8_t *solid, void *geom, int nx, int 
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(finalize_sums, dim3(1), dim3(256), 0, st, partials, nblocks, out);
+hipError_t launch_finalize(const double *partials, int nblocks, double *stage, double *out, hipStream_t st) {
+  const int nb1 = nblocks < 256 ? nblocks : 256;
+  const int chunk = (nblocks + nb1 - 1) / nb1;
+  hipLaunchKernelGGL(finalize_stage, dim3(nb1), dim3(256), 0, st, partials, nblocks, chunk, stage);
+  hipLaunchKernelGGL(finalize_stage, dim3(1), dim3(256), 0, st, (const double *)stage, nb1, nb1, out);
   return hipGetLastError();
 }
 }  // namespace lbm

@@ -51,6 +51,10 @@ template <class St, class R> __device__ __forceinline__ St encode(R v) { return 
 // status of a neighbour position for the stencils and the links
 enum : int { ST_FLUID = 0, ST_SOLID = 1, ST_INLET = 2, ST_OUTLET = 3 };
 
+// Division: IEEE in FP64; in FP32 the hardware reciprocal (1 ulp) times the numerator.
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // ------------------------------------------------------------------------ 1-D chimera
 // Central moments of orders 0,1,2 about u of a 3-point distribution on {-1,0,+1}
 // (Geier et al. 2015, the 1-D factor of the D2Q9/D3Q27 moment transform), in place.
@@ -87,10 +91,10 @@ template <class R> struct Rates {
 template <class R>
 __device__ __forceinline__ R shear_rate(const Rates<R> &r, R PiPi) {
   // tau = (tau0 + sqrt(tau0^2 + 2 Cs^2 Qbar / cs2^2)) / 2, Qbar = sqrt(2 Pi:Pi)
-  if (r.smag18 == R(0)) return R(1) / r.tau0;
+  if (r.smag18 == R(0)) return fdiv(R(1), r.tau0);
   const R Qbar = sqrt(R(2) * PiPi);
   const R tau = R(0.5) * (r.tau0 + sqrt(r.tau0 * r.tau0 + r.smag18 * Qbar));
-  return R(1) / tau;
+  return fdiv(R(1), tau);
 }
 
 template <class R>
@@ -266,32 +270,39 @@ __device__ __forceinline__ R pipi_of(const R (&d)[Q], const R (&u)[3]) {
 // ------------------------------------------------------------------------ scalars
 // Physics selected by the number of transported scalars: 0 isothermal, 1 passive
 // temperature, 2 (T, Y_fuel) one-step, 6 (T, CH4, O2, CO, CO2, H2O) two-step.
-struct Thermo {
-  double rho_ref, T_ref, nu_ref, inv_Pr, F, visc_const_mu;
-  double chem[32];
+template <class R> struct ThermoT {
+  R rho_ref, nu_ref, mu_ref, inv_Pr, F, invF;
+  int const_mu;          // 1: nu = mu_ref / rho, 0: nu = nu_ref
+  R rhoT;                // rho_ref T_ref (one-step: rho = rhoT / T)
+  R rhoT_W;              // rho_ref T_ref / W_ref (two-step: rho = rhoT_W W / T)
+  R B1, Ta1, B2, Ta2;    // Arrhenius factors and activation temperatures
+  R heat1;               // one-step: (T_ad - T_u)/Y_u
+  R inv_cp;
+  R W[6], inv_W[6], h[6];
 };
 
+
 template <int NS, class R>
-__device__ __forceinline__ R density(const Thermo &t, const R (&v)[NS > 0 ? NS : 1]) {
+__device__ __forceinline__ R density(const ThermoT<R> &t, const R (&v)[NS > 0 ? NS : 1]) {
   if constexpr (NS <= 1) {
-    return R(t.rho_ref);
+    return t.rho_ref;
   } else if constexpr (NS == 2) {
-    return R(t.rho_ref * t.T_ref) / v[0];
+    return fdiv(t.rhoT, v[0]);
   } else {
     // rho = rho_ref (T_ref/T)(W/W_ref), 1/W = sum Y_k/W_k with N2 by closure
     R ysum = R(0), inv = R(0);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       ysum += v[1 + k];
-      inv += v[1 + k] * R(1.0 / t.chem[5 + k]);
+      inv += v[1 + k] * t.inv_W[k];
     }
-    inv += (R(1) - ysum) * R(1.0 / t.chem[10]);
-    return R(t.rho_ref * t.T_ref / t.chem[17]) / (v[0] * inv);
+    inv += (R(1) - ysum) * t.inv_W[5];
+    return fdiv(t.rhoT_W, v[0] * inv);
   }
 }
 
-template <class R> __device__ __forceinline__ R viscosity(const Thermo &t, R rho) {
-  return t.visc_const_mu != 0.0 ? R(t.nu_ref * t.rho_ref) / rho : R(t.nu_ref);
+template <class R> __device__ __forceinline__ R viscosity(const ThermoT<R> &t, R rho) {
+  return t.const_mu ? fdiv(t.mu_ref, rho) : t.nu_ref;
 }
 
 // Jiang-Shu WENO3 face value between b and c from the upwind-biased triple (a, b, c).
@@ -299,7 +310,7 @@ template <class R> __device__ __forceinline__ R weno3_face(R a, R b, R c, R eps)
   const R b0 = (b - a) * (b - a), b1 = (c - b) * (c - b);
   const R e0 = eps + b0, e1 = eps + b1;
   const R a0 = R(1.0 / 3.0) * e1 * e1, a1 = R(2.0 / 3.0) * e0 * e0;   // alpha ratios
-  return (a0 * (R(-0.5) * a + R(1.5) * b) + a1 * (R(0.5) * b + R(0.5) * c)) / (a0 + a1);
+  return fdiv(a0 * (R(-0.5) * a + R(1.5) * b) + a1 * (R(0.5) * b + R(0.5) * c), a0 + a1);
 }
 
 }  // namespace lbm

@@ -15,17 +15,19 @@ hipError_t launch_d3q27(int prec, int ns, int kind, const StepArgs &a, int nbloc
                         const double *Ph, const double *u, const double *scal);
 hipError_t launch_geometry(int Q, const uint8_t *solid, void *geom, int nx, int ny, int nz, long long N,
                            const int *face, hipStream_t st);
-hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t st);
+hipError_t launch_finalize(const double *partials, int nblocks, double *stage, double *out, hipStream_t st);
 
 template <int Q, int PREC, int NS>
 hipError_t launch_one(int kind, const StepArgs &a, int nblocks, hipStream_t st, const double *Ph,
                       const double *u, const double *scal) {
+  using R = typename Prec<PREC>::R;
   if (kind == LAUNCH_STEP)
-    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false>), dim3(nblocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
   else if (kind == LAUNCH_EXTRACT)
-    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true>), dim3(nblocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
   else
-    hipLaunchKernelGGL((init_kernel<Q, PREC, NS>), dim3(nblocks), dim3(256), 0, st, a, Ph, u, scal);
+    hipLaunchKernelGGL((init_kernel<Q, PREC, NS>), dim3(nblocks), dim3(256), 0, st, to_kargs<double>(a), Ph,
+                       u, scal);
   return hipGetLastError();
 }
 

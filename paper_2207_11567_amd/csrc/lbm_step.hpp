@@ -11,9 +11,17 @@
 //   -> FP64 block partial sums (wavefront shuffles + LDS), one record per block.
 #pragma once
 
+#include <type_traits>
+
 #include "lbm_device.hpp"
 
 namespace lbm {
+
+// Host-side description of one launch (double precision constants).
+struct Thermo {
+  double rho_ref, T_ref, nu_ref, inv_Pr, F, visc_const_mu;
+  double chem[32];
+};
 
 struct StepArgs {
   const void *pop_in;
@@ -38,6 +46,63 @@ struct StepArgs {
   unsigned long long seed;
   Thermo th;
 };
+
+// Kernel arguments with every floating constant already in the compute precision R, so
+// that the kernel reads uniform values straight from the argument segment.
+template <class R> struct KArgs {
+  const void *pop_in;
+  void *pop_out;
+  const void *scal_in;
+  void *scal_out;
+  const void *geom;
+  double *partials;
+  int *flag;
+  double *f_P, *f_rho, *f_u, *f_scal;
+  int nx, ny, nz, N;
+  int face[6];
+  long long step;
+  int collision, remap;
+  R P0, invP0, wb, wh, smag18;
+  R inlet_u[3], outlet_P;
+  double inlet_noise;
+  R phi_in[8], eps[8];
+  unsigned long long seed;
+  double inv_T_ref_d, W_d[6];
+  ThermoT<R> th;
+};
+
+template <class R> KArgs<R> to_kargs(const StepArgs &a) {
+  KArgs<R> k;
+  k.pop_in = a.pop_in; k.pop_out = a.pop_out; k.scal_in = a.scal_in; k.scal_out = a.scal_out;
+  k.geom = a.geom; k.partials = a.partials; k.flag = a.flag;
+  k.f_P = a.f_P; k.f_rho = a.f_rho; k.f_u = a.f_u; k.f_scal = a.f_scal;
+  k.nx = a.nx; k.ny = a.ny; k.nz = a.nz; k.N = (int)a.N;
+  for (int f = 0; f < 6; ++f) k.face[f] = a.face[f];
+  k.step = a.step; k.collision = a.collision; k.remap = a.remap;
+  k.P0 = (R)a.P0; k.invP0 = (R)(1.0 / a.P0); k.wb = (R)a.wb; k.wh = (R)a.wh; k.smag18 = (R)a.smag18;
+  for (int d = 0; d < 3; ++d) k.inlet_u[d] = (R)a.inlet_u[d];
+  k.outlet_P = (R)a.outlet_P; k.inlet_noise = a.inlet_noise;
+  for (int q = 0; q < 8; ++q) { k.phi_in[q] = (R)a.phi_in[q]; k.eps[q] = (R)a.eps[q]; }
+  k.seed = a.seed;
+  const double *ch = a.th.chem;
+  k.inv_T_ref_d = 1.0 / a.th.T_ref;
+  for (int q = 0; q < 6; ++q) k.W_d[q] = ch[5 + q] > 0.0 ? ch[5 + q] : 1.0;
+  ThermoT<R> &t = k.th;
+  t.rho_ref = (R)a.th.rho_ref; t.nu_ref = (R)a.th.nu_ref; t.mu_ref = (R)(a.th.nu_ref * a.th.rho_ref);
+  t.inv_Pr = (R)a.th.inv_Pr; t.F = (R)a.th.F; t.invF = (R)(1.0 / a.th.F);
+  t.const_mu = a.th.visc_const_mu != 0.0;
+  t.rhoT = (R)(a.th.rho_ref * a.th.T_ref);
+  t.rhoT_W = (R)(ch[17] > 0.0 ? a.th.rho_ref * a.th.T_ref / ch[17] : 0.0);
+  t.B1 = (R)ch[0]; t.Ta1 = (R)ch[1]; t.B2 = (R)ch[2]; t.Ta2 = (R)ch[3];
+  t.heat1 = (R)(ch[4] > 0.0 ? (ch[3] - ch[2]) / ch[4] : 0.0);
+  t.inv_cp = (R)(ch[4] > 0.0 ? 1.0 / ch[4] : 0.0);
+  for (int q = 0; q < 6; ++q) {
+    t.W[q] = (R)ch[5 + q];
+    t.inv_W[q] = (R)(ch[5 + q] > 0.0 ? 1.0 / ch[5 + q] : 0.0);
+    t.h[q] = (R)ch[11 + q];
+  }
+  return k;
+}
 
 template <int Q> struct GeomWord { using T = uint64_t; };
 template <> struct GeomWord<9> { using T = uint32_t; };
@@ -91,30 +156,40 @@ __device__ __forceinline__ AxisNb axis_nb(int c, int n, int flo, int fhi) {
   return r;
 }
 
-template <class T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
+// Element access through a wave-uniform base pointer and a 32-bit byte offset, so that
+// the compiler can address with the scalar base + vector offset form.
+template <class T> __device__ __forceinline__ T ldg(const T *base, unsigned idx) {
+  return *(const T *)((const char *)base + idx * (unsigned)sizeof(T));
+}
+template <class T> __device__ __forceinline__ void stg(T *base, unsigned idx, T v) {
+  *(T *)((char *)base + idx * (unsigned)sizeof(T)) = v;
+}
 
-// Block reduction of 8 doubles into partials[tile*8 ..]: wavefront shuffles, then LDS.
+
+// Block reduction of 8 doubles into partials[tile*8 ..] in a fixed order: every thread
+// parks its values in LDS, then lane t of wave 0 sums 32 cells of counter t/8, and the 8
+// lanes of each counter combine by xor-shuffles.  256 threads per block.
 __device__ __forceinline__ void block_sums(double (&v)[8], double *out) {
-  __shared__ double sh[8][8];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ double sh[8][256];
+  const int t = threadIdx.x;
+  const int slot = (t & 31) * 8 + (t >> 5);          // part (t>>5) of 8, element t&31
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0) sh[wv][k] = x;
-  }
+  for (int k = 0; k < 8; ++k) sh[k][slot] = v[k];
   __syncthreads();
-  if (threadIdx.x < 8) {
-    const int nw = (blockDim.x + 63) >> 6;
+  if (t < 64) {
+    const int k = t >> 3, part = t & 7;
     double acc = 0.0;
-    for (int w = 0; w < nw; ++w) acc += sh[w][threadIdx.x];
-    out[threadIdx.x] = acc;
+#pragma unroll 8
+    for (int j = 0; j < 32; ++j) acc += sh[k][j * 8 + part];
+    acc += __shfl_xor(acc, 4, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 1, 64);
+    if (part == 0) out[k] = acc;
   }
 }
 
 template <int Q, int PREC, int NS, bool EXTRACT>
-__global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
+__global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R> a) {
   using P = Prec<PREC>;
   using St = typename P::St;
   using R = typename P::R;
@@ -125,18 +200,21 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   constexpr R s = R(1.0 / 3.0);
 
   const int tile = tile_of_block(blockIdx.x, gridDim.x, a.remap);
-  const long long n = (long long)tile * blockDim.x + threadIdx.x;
+  const int n = tile * (int)blockDim.x + (int)threadIdx.x;
   double red[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const long long N = a.N;
+  const int N = a.N;
+  const unsigned un = (unsigned)n;
   const St *__restrict__ pin = (const St *)a.pop_in;
   St *__restrict__ pout = (St *)a.pop_out;
   const Sc *__restrict__ sin_ = (const Sc *)a.scal_in;
   Sc *__restrict__ sout = (Sc *)a.scal_out;
 
   if (n < N) {
-    const int x = (int)(n % a.nx);
-    const int y = (int)((n / a.nx) % a.ny);
-    const int z = (int)(n / ((long long)a.nx * a.ny));
+    const int nxy = a.nx * a.ny;
+    const int z = n / nxy;
+    const int rem = n - z * nxy;
+    const int y = rem / a.nx;
+    const int x = rem - y * a.nx;
     const GW gw = a.geom ? ((const GW *)a.geom)[n] : GW(0);
     if (gw & (GW(1) << bit_self<Q>())) {
       if (!EXTRACT) {
@@ -155,136 +233,61 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
           for (int k = 0; k < NS; ++k) a.f_scal[k * N + n] = (double)sin_[k * N + n];
       }
     } else {
-      const AxisNb ax = axis_nb(x, a.nx, a.face[0], a.face[1]);
-      const AxisNb ay = axis_nb(y, a.ny, a.face[2], a.face[3]);
-      const AxisNb az = D == 3 ? axis_nb(z, a.nz, a.face[4], a.face[5]) : AxisNb{{z, z, z, z, z}, {-1, -1, -1, -1, -1}};
-      auto lin = [&](int X, int Y, int Z) -> long long {
-        return (long long)X + (long long)a.nx * ((long long)Y + (long long)a.ny * Z);
-      };
-      // status of position k (= -2..2) along axis d
-      auto status = [&](int d, int k) -> int {
-        const AxisNb &A = d == 0 ? ax : d == 1 ? ay : az;
-        const int c = A.code[k + 2];
-        if (c >= 0) return c;
-        if (k == 1) return (gw >> link_from_plus<Q>(d)) & 1 ? ST_SOLID : ST_FLUID;
-        if (k == -1) return (gw >> link_from_minus<Q>(d)) & 1 ? ST_SOLID : ST_FLUID;
-        if (k == 2) return (gw >> bit_far<Q>(d, 0)) & 1 ? ST_SOLID : ST_FLUID;
-        return (gw >> bit_far<Q>(d, 1)) & 1 ? ST_SOLID : ST_FLUID;
-      };
-      auto nb_index = [&](int d, int k) -> long long {
-        return d == 0 ? lin(ax.idx[k + 2], y, z) : d == 1 ? lin(x, ay.idx[k + 2], z) : lin(x, y, az.idx[k + 2]);
-      };
-
-      // ---------------------------------------------------------------- scalars at n
-      R phi0[NSV];
-      R rho0 = R(a.th.rho_ref);
-      R R_s[NSV];
-      R gradrho[3] = {R(0), R(0), R(0)};
-      R Lam = R(0);
-      R phin[NSV];
+      // neighbour offsets (relative linear index) and face codes for k = -2..2 per axis
+      int off[3][5], code[3][5];
+      {
+        const AxisNb ax = axis_nb(x, a.nx, a.face[0], a.face[1]);
+        const AxisNb ay = axis_nb(y, a.ny, a.face[2], a.face[3]);
 #pragma unroll
-      for (int k = 0; k < NSV; ++k) { phi0[k] = R(0); R_s[k] = R(0); phin[k] = R(a.phi_in[k]); }
-      if constexpr (NS > 0) {
-#pragma unroll
-        for (int k = 0; k < NS; ++k) phi0[k] = (R)sin_[k * N + n];
-        rho0 = density<NS, R>(a.th, phi0);
-        const R rhoD0 = rho0 * viscosity(a.th, rho0) * R(a.th.inv_Pr);
-        const R rho_in = density<NS, R>(a.th, phin);
-        const R rhoD_in = rho_in * viscosity(a.th, rho_in) * R(a.th.inv_Pr);
-        R diff[NSV];
-#pragma unroll
-        for (int k = 0; k < NS; ++k) diff[k] = R(0);
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          R rk[2];
-#pragma unroll
-          for (int side = 0; side < 2; ++side) {
-            const int k = side == 0 ? 1 : -1;
-            const int st = status(d, k);
-            R v[NSV];
-            if (st == ST_FLUID) {
-              const long long m = nb_index(d, k);
-#pragma unroll
-              for (int q = 0; q < NS; ++q) v[q] = (R)sin_[q * N + m];
-            } else {
-#pragma unroll
-              for (int q = 0; q < NS; ++q) v[q] = st == ST_INLET ? phin[q] : phi0[q];
-            }
-            R rhok = rho0;
-            if (st == ST_FLUID) rhok = density<NS, R>(a.th, v);
-            else if (st == ST_INLET) rhok = rho_in;
-            rk[side] = rhok;
-            if (st == ST_FLUID || st == ST_INLET) {
-              const R rDk = st == ST_INLET ? rhoD_in : rhok * viscosity(a.th, rhok) * R(a.th.inv_Pr);
-              const R cf = R(0.5) * (rhoD0 + rDk);
-#pragma unroll
-              for (int q = 0; q < NS; ++q) diff[q] += cf * (v[q] - phi0[q]);
-            }
-          }
-          gradrho[d] = R(0.5) * (rk[0] - rk[1]);
+        for (int k = 0; k < 5; ++k) {
+          off[0][k] = ax.idx[k] - x;
+          code[0][k] = ax.code[k];
+          off[1][k] = (ay.idx[k] - y) * a.nx;
+          code[1][k] = ay.code[k];
+          off[2][k] = 0;
+          code[2][k] = -1;
         }
-        const R Fr = R(a.th.F) / rho0;
+        if (D == 3) {
+          const AxisNb az = axis_nb(z, a.nz, a.face[4], a.face[5]);
 #pragma unroll
-        for (int q = 0; q < NS; ++q) R_s[q] = Fr * diff[q];
-        // chemistry (reaction over F) and Lambda
-        const R invF = R(1.0 / a.th.F);
-        if constexpr (NS == 2) {
-          const double *ch = a.th.chem;
-          const R r = R(ch[0]) * fmax(phi0[1], R(0)) * exp(-R(ch[1]) / phi0[0]);
-          R_s[0] += R((ch[3] - ch[2]) / ch[4]) * r * invF;
-          R_s[1] -= r * invF;
-          Lam = R_s[0] / phi0[0];
-        } else if constexpr (NS == 6) {
-          const double *ch = a.th.chem;
-          R conc[5];
-#pragma unroll
-          for (int q = 0; q < 5; ++q) conc[q] = rho0 * fmax(phi0[1 + q], R(0)) * R(1.0 / ch[5 + q]);
-          const R T = phi0[0];
-          const R q1 = R(ch[0]) * exp(-R(ch[1]) / T) * conc[0] * conc[1];
-          const R q2 = R(ch[2]) * exp(-R(ch[3]) / T) * conc[2] * sqrt(conc[1]);
-          const R ir = R(1) / rho0;
-          // molar rates per mass: nu_k1 q1 + nu_k2 q2 over rho
-          const R m0 = -q1 * ir, m1 = (R(-1.5) * q1 - R(0.5) * q2) * ir, m2 = (q1 - q2) * ir,
-                  m3 = q2 * ir, m4 = R(2) * q1 * ir;
-          R_s[1] += R(ch[5]) * m0 * invF;
-          R_s[2] += R(ch[6]) * m1 * invF;
-          R_s[3] += R(ch[7]) * m2 * invF;
-          R_s[4] += R(ch[8]) * m3 * invF;
-          R_s[5] += R(ch[9]) * m4 * invF;
-          const R heat = -(R(ch[11]) * m0 + R(ch[12]) * m1 + R(ch[13]) * m2 + R(ch[14]) * m3 +
-                           R(ch[15]) * m4) * R(1.0 / ch[4]);
-          R_s[0] += heat * invF;
-          // Lambda = R_T/T + W sum_k R_k/W_k (N2 by closure: R_N2 = -sum R_k)
-          R ysum = R(0), invW = R(0), acc = R(0), rsum = R(0);
-#pragma unroll
-          for (int q = 0; q < 5; ++q) {
-            ysum += phi0[1 + q];
-            invW += phi0[1 + q] * R(1.0 / ch[5 + q]);
-            acc += R_s[1 + q] * R(1.0 / ch[5 + q]);
-            rsum += R_s[1 + q];
+          for (int k = 0; k < 5; ++k) {
+            off[2][k] = (az.idx[k] - z) * nxy;
+            code[2][k] = az.code[k];
           }
-          invW += (R(1) - ysum) * R(1.0 / ch[10]);
-          acc -= rsum * R(1.0 / ch[10]);
-          Lam = R_s[0] / T + acc / invW;
         }
       }
+      // status of the axis neighbours at -2, -1, +1, +2
+      auto status = [&](int d, int k) -> int {
+        const int c = code[d][k + 2];
+        if (c >= 0) return c;
+        const int b = k == 1 ? link_from_plus<Q>(d) : k == -1 ? link_from_minus<Q>(d) : bit_far<Q>(d, k < 0 ? 1 : 0);
+        return (gw >> b) & 1 ? ST_SOLID : ST_FLUID;
+      };
+
+      // ---------------------------------------------------------------- cell scalars, rho
+      R phi0[NSV], phin[NSV];
+#pragma unroll
+      for (int k = 0; k < NSV; ++k) { phi0[k] = R(0); phin[k] = R(a.phi_in[k]); }
+#pragma unroll
+      for (int k = 0; k < NS; ++k) phi0[k] = (R)ldg(sin_ + (size_t)k * N, un);
+      const R rho0 = NS > 0 ? density<NS, R>(a.th, phi0) : R(a.th.rho_ref);
+      const R rho_in = NS > 0 ? density<NS, R>(a.th, phin) : R(a.th.rho_ref);
 
       // ---------------------------------------------------------------- pull (Eq. 1)
       R gh[Q];
-      const bool border = ax.code[1] >= 0 || ax.code[3] >= 0 || ay.code[1] >= 0 || ay.code[3] >= 0 ||
-                          (D == 3 && (az.code[1] >= 0 || az.code[3] >= 0));
+      const bool border = code[0][1] >= 0 || code[0][3] >= 0 || code[1][1] >= 0 || code[1][3] >= 0 ||
+                          (D == 3 && (code[2][1] >= 0 || code[2][3] >= 0));
       constexpr GW linkmask = (GW(1) << Q) - GW(1);
       if (!border && !(gw & linkmask)) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const long long m = lin(ax.idx[2 - cx(i)], ay.idx[2 - cy(i)], D == 3 ? az.idx[2 - cz(i)] : z);
-          gh[i] = decode<R>(pin[i * N + m]);
+          const unsigned m = un + (unsigned)(off[0][2 - cx(i)] + off[1][2 - cy(i)] + (D == 3 ? off[2][2 - cz(i)] : 0));
+          gh[i] = decode<R>(ldg(pin + (size_t)i * N, m));
         }
       } else {
         // boundary cell: bounce-back, moving-wall inlet, anti-bounce-back outlet
         R uw_in[3] = {R(a.inlet_u[0]), R(a.inlet_u[1]), R(a.inlet_u[2])};
         if (a.inlet_noise != 0.0) {
-          // in-face coordinates of the inlet face
           int fa = -1;
 #pragma unroll
           for (int d = 0; d < D; ++d)
@@ -292,14 +295,12 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
           if (fa >= 0) {
             const int c3[3] = {x, y, z};
             const int o0 = fa == 0 ? 1 : 0, o1 = fa == 2 ? 1 : 2;
-            const double xi = splitmix_xi(a.seed, (unsigned long long)c3[o0],
-                                          (unsigned long long)c3[o1], (unsigned long long)a.step);
+            const double xi = splitmix_xi(a.seed, (unsigned long long)c3[o0], (unsigned long long)c3[o1],
+                                          (unsigned long long)a.step);
             const R sc = R(1.0 + a.inlet_noise * xi);
             uw_in[0] *= sc; uw_in[1] *= sc; uw_in[2] *= sc;
           }
         }
-        const R rho_in = NS > 0 ? density<NS, R>(a.th, phin) : R(a.th.rho_ref);
-        // outlet: velocity of the cell's own post-collision populations, rho at n
         R uo[3] = {R(0), R(0), R(0)};
         bool has_out = false;
 #pragma unroll
@@ -307,16 +308,16 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
         if (has_out) {
 #pragma unroll
           for (int j = 0; j < Q; ++j) {
-            const R gj = decode<R>(pin[j * N + n]);
+            const R gj = decode<R>(ldg(pin + (size_t)j * N, un));
             uo[0] += R(cx(j)) * gj;
             uo[1] += R(cy(j)) * gj;
             if (D == 3) uo[2] += R(cz(j)) * gj;
           }
-          const R f = R(a.P0) / (s * rho0);
+          const R f = fdiv(a.P0, s * rho0);
           uo[0] *= f; uo[1] *= f; uo[2] *= f;
         }
         const R uo2 = uo[0] * uo[0] + uo[1] * uo[1] + uo[2] * uo[2];
-        const R invP0 = R(1.0 / a.P0);
+        const R invP0 = a.invP0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const int c[3] = {cx(i), cy(i), D == 3 ? cz(i) : 0};
@@ -324,31 +325,30 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
 #pragma unroll
           for (int d = 0; d < D; ++d) {
             if (c[d] == 0) continue;
-            const AxisNb &A = d == 0 ? ax : d == 1 ? ay : az;
-            const int code = A.code[2 - c[d]];
-            wall |= code == ST_SOLID;
-            inl |= code == ST_INLET;
-            outl |= code == ST_OUTLET;
+            const int cd = code[d][2 - c[d]];
+            wall |= cd == ST_SOLID;
+            inl |= cd == ST_INLET;
+            outl |= cd == ST_OUTLET;
           }
           const bool solid_src = (gw >> i) & 1;
           const int io = Q - 1 - i;
           if (wall || (!inl && !outl && solid_src)) {
-            gh[i] = decode<R>(pin[io * N + n]);
+            gh[i] = decode<R>(ldg(pin + (size_t)io * N, un));
           } else if (inl) {
             const R cu = R(c[0]) * uw_in[0] + R(c[1]) * uw_in[1] + R(c[2]) * uw_in[2];
-            gh[i] = decode<R>(pin[io * N + n]) + R(2.0 * wgt<Q>(i)) * rho_in * cu * invP0;
+            gh[i] = decode<R>(ldg(pin + (size_t)io * N, un)) + R(2.0 * wgt<Q>(i)) * rho_in * cu * invP0;
           } else if (outl) {
             const R cu = R(c[0]) * uo[0] + R(c[1]) * uo[1] + R(c[2]) * uo[2];
-            gh[i] = -decode<R>(pin[io * N + n]) +
+            gh[i] = -decode<R>(ldg(pin + (size_t)io * N, un)) +
                     R(2.0 * wgt<Q>(i)) * ((R(a.outlet_P) + rho0 * (cu * cu * R(1.5) - uo2 * R(0.5))) * invP0 - R(1));
           } else {
-            const long long m = lin(ax.idx[2 - c[0]], ay.idx[2 - c[1]], D == 3 ? az.idx[2 - c[2]] : z);
-            gh[i] = decode<R>(pin[i * N + m]);
+            const unsigned m = un + (unsigned)(off[0][2 - c[0]] + off[1][2 - c[1]] + (D == 3 ? off[2][2 - c[2]] : 0));
+            gh[i] = decode<R>(ldg(pin + (size_t)i * N, m));
           }
         }
       }
 
-      // ---------------------------------------------------------------- moments (Eq. 7)
+      // ---------------------------------------------------------------- moments (Eq. 7b)
       R sg = R(0), mx = R(0), my = R(0), mz = R(0);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
@@ -358,9 +358,139 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
         if (D == 3 && cz(i)) mz += R(cz(i)) * gh[i];
       }
       const R P0 = R(a.P0);
-      const R mom = P0 / (s * rho0);             // rho u = P0 sum c ghat / cs2
-      R u[3] = {mx * mom, my * mom, D == 3 ? mz * mom : R(0)};
-      const R Ph = P0 * (sg + R(1)) + R(0.5) * rho0 * s * Lam;
+      const R mom = fdiv(P0, s * rho0);          // rho u = P0 sum c ghat / cs2
+      const R u[3] = {mx * mom, my * mom, D == 3 ? mz * mom : R(0)};
+
+      // ---------------------------------------------------------------- scalar stencils
+      // One pass per axis: the five stencil values of every scalar (ghost rules at walls,
+      // inlet, outlet), density at +-1 for grad rho and the diffusion coefficients, the
+      // centred diffusion fluxes and the WENO3 advective derivative.
+      R gradrho[3] = {R(0), R(0), R(0)};
+      R Lam = R(0);
+      R R_s[NSV], adv[NSV];
+#pragma unroll
+      for (int k = 0; k < NSV; ++k) { R_s[k] = R(0); adv[k] = R(0); }
+      if constexpr (NS > 0) {
+        const R rhoD0 = rho0 * viscosity(a.th, rho0) * a.th.inv_Pr;
+        const R rhoD_in = rho_in * viscosity(a.th, rho_in) * a.th.inv_Pr;
+        // cells whose +-2 stencil touches no face and no solid take the plain path
+        bool interior = gw == GW(0);
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+          interior = interior && code[d][0] < 0 && code[d][1] < 0 && code[d][3] < 0 && code[d][4] < 0;
+        auto stencils = [&](auto fast_tag) {
+          constexpr bool FAST = decltype(fast_tag)::value;
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            const int sp1 = FAST ? ST_FLUID : status(d, 1), sm1 = FAST ? ST_FLUID : status(d, -1);
+            const int sp2 = FAST ? ST_FLUID : status(d, 2), sm2 = FAST ? ST_FLUID : status(d, -2);
+            const unsigned mp1 = un + (unsigned)off[d][3], mm1 = un + (unsigned)off[d][1];
+            const unsigned mp2 = un + (unsigned)off[d][4], mm2 = un + (unsigned)off[d][0];
+            const R ud = u[d];
+            const bool up = ud >= R(0);
+            R vp1[NSV], vm1[NSV];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+              const Sc *sq = sin_ + (size_t)q * N;
+              if (FAST) {
+                vp1[q] = (R)ldg(sq, mp1);
+                vm1[q] = (R)ldg(sq, mm1);
+              } else {
+                vp1[q] = sp1 == ST_FLUID ? (R)ldg(sq, mp1) : sp1 == ST_INLET ? phin[q] : phi0[q];
+                vm1[q] = sm1 == ST_FLUID ? (R)ldg(sq, mm1) : sm1 == ST_INLET ? phin[q] : phi0[q];
+              }
+            }
+            // density at +-1 and diffusion through the two faces
+            R rp = rho0, rm = rho0;
+            if (FAST || sp1 == ST_FLUID) rp = density<NS, R>(a.th, vp1); else if (sp1 == ST_INLET) rp = rho_in;
+            if (FAST || sm1 == ST_FLUID) rm = density<NS, R>(a.th, vm1); else if (sm1 == ST_INLET) rm = rho_in;
+            gradrho[d] = R(0.5) * (rp - rm);
+            R cfp, cfm;
+            if (FAST) {
+              cfp = R(0.5) * (rhoD0 + rp * viscosity(a.th, rp) * a.th.inv_Pr);
+              cfm = R(0.5) * (rhoD0 + rm * viscosity(a.th, rm) * a.th.inv_Pr);
+            } else {
+              const bool fp = sp1 == ST_FLUID || sp1 == ST_INLET, fm = sm1 == ST_FLUID || sm1 == ST_INLET;
+              cfp = fp ? R(0.5) * (rhoD0 + (sp1 == ST_INLET ? rhoD_in : rp * viscosity(a.th, rp) * a.th.inv_Pr)) : R(0);
+              cfm = fm ? R(0.5) * (rhoD0 + (sm1 == ST_INLET ? rhoD_in : rm * viscosity(a.th, rm) * a.th.inv_Pr)) : R(0);
+            }
+#pragma unroll
+            for (int q = 0; q < NS; ++q) R_s[q] += cfp * (vp1[q] - phi0[q]) + cfm * (vm1[q] - phi0[q]);
+            if (!EXTRACT) {
+              // WENO3 upwinded on the sign of u_d, written branch-free: with the upwind
+              // neighbours U1, U2 and the downwind neighbour D1,
+              // u_d dphi/dx_d = |u_d| (face(U1, 0, D1) - face(U2, U1, 0)).
+              const R au = fabs(ud);
+              const unsigned mfar = up ? mm2 : mp2;
+#pragma unroll
+              for (int q = 0; q < NS; ++q) {
+                const Sc *sq = sin_ + (size_t)q * N;
+                const R v0 = phi0[q];
+                R vU2;
+                if (FAST) {
+                  vU2 = (R)ldg(sq, mfar);
+                } else {
+                  R vm2, vp2;
+                  if (sm1 == ST_FLUID) vm2 = sm2 == ST_FLUID ? (R)ldg(sq, mm2) : sm2 == ST_INLET ? phin[q] : vm1[q];
+                  else vm2 = sm1 == ST_SOLID ? vp1[q] : sm1 == ST_INLET ? phin[q] : v0;
+                  if (sp1 == ST_FLUID) vp2 = sp2 == ST_FLUID ? (R)ldg(sq, mp2) : sp2 == ST_INLET ? phin[q] : vp1[q];
+                  else vp2 = sp1 == ST_SOLID ? vm1[q] : sp1 == ST_INLET ? phin[q] : v0;
+                  vU2 = up ? vm2 : vp2;
+                }
+                const R vU1 = up ? vm1[q] : vp1[q];
+                const R vD1 = up ? vp1[q] : vm1[q];
+                adv[q] += au * (weno3_face(vU1, v0, vD1, a.eps[q]) - weno3_face(vU2, vU1, v0, a.eps[q]));
+              }
+            }
+          }
+        };
+        if (interior) stencils(std::true_type{});
+        else stencils(std::false_type{});
+        const R Fr = fdiv(a.th.F, rho0);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) R_s[q] *= Fr;
+        // chemistry (reaction over F) and Lambda (Eq. 3)
+        const R invF = a.th.invF;
+        if constexpr (NS == 2) {
+          const R r = a.th.B1 * fmax(phi0[1], R(0)) * exp(-fdiv(a.th.Ta1, phi0[0]));
+          R_s[0] += a.th.heat1 * r * invF;
+          R_s[1] -= r * invF;
+          Lam = fdiv(R_s[0], phi0[0]);
+        } else if constexpr (NS == 6) {
+          R conc[5];
+#pragma unroll
+          for (int q = 0; q < 5; ++q) conc[q] = rho0 * fmax(phi0[1 + q], R(0)) * a.th.inv_W[q];
+          const R T = phi0[0];
+          const R iT = fdiv(R(1), T);
+          const R q1 = a.th.B1 * exp(-a.th.Ta1 * iT) * conc[0] * conc[1];
+          const R q2 = a.th.B2 * exp(-a.th.Ta2 * iT) * conc[2] * sqrt(conc[1]);
+          const R ir = fdiv(R(1), rho0);
+          // molar rates per mass: sum over reactions of nu_k,r q_r, over rho
+          const R m0 = -q1 * ir, m1 = (R(-1.5) * q1 - R(0.5) * q2) * ir, m2 = (q1 - q2) * ir,
+                  m3 = q2 * ir, m4 = R(2) * q1 * ir;
+          R_s[1] += a.th.W[0] * m0 * invF;
+          R_s[2] += a.th.W[1] * m1 * invF;
+          R_s[3] += a.th.W[2] * m2 * invF;
+          R_s[4] += a.th.W[3] * m3 * invF;
+          R_s[5] += a.th.W[4] * m4 * invF;
+          const R heat = -(a.th.h[0] * m0 + a.th.h[1] * m1 + a.th.h[2] * m2 + a.th.h[3] * m3 +
+                           a.th.h[4] * m4) * a.th.inv_cp;
+          R_s[0] += heat * invF;
+          // Lambda = R_T/T + W sum_k R_k/W_k (N2 by closure: R_N2 = -sum R_k)
+          R ysum = R(0), invW = R(0), acc = R(0), rsum = R(0);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            ysum += phi0[1 + q];
+            invW += phi0[1 + q] * a.th.inv_W[q];
+            acc += R_s[1 + q] * a.th.inv_W[q];
+            rsum += R_s[1 + q];
+          }
+          invW += (R(1) - ysum) * a.th.inv_W[5];
+          acc -= rsum * a.th.inv_W[5];
+          Lam = R_s[0] * iT + fdiv(acc, invW);
+        }
+      }
+      const R Ph = P0 * (sg + R(1)) + R(0.5) * rho0 * s * Lam;   // Eq. 7a
 
       if (EXTRACT) {
         if (a.f_P) a.f_P[n] = (double)Ph;
@@ -371,108 +501,73 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
         if (a.f_scal)
 #pragma unroll
           for (int k = 0; k < NS; ++k) a.f_scal[k * N + n] = (double)phi0[k];
-      }
-
-      // ---------------------------------------------------------------- scalar update
-      bool bad = false;
-      if constexpr (NS > 0) {
-        if (!EXTRACT) {
+      } else {
+        // ------------------------------------------------------------ scalar update
+        bool bad = false;
 #pragma unroll
-          for (int q = 0; q < NS; ++q) {
-            R adv = R(0);
-            const R eps = R(a.eps[q]);
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-              const int s1 = status(d, 1), sm1 = status(d, -1);
-              const int s2 = status(d, 2), sm2 = status(d, -2);
-              const R v0 = phi0[q];
-              const R pin_q = phin[q];
-              R vp1 = v0, vm1 = v0;
-              if (s1 == ST_FLUID) vp1 = (R)sin_[q * N + nb_index(d, 1)];
-              else if (s1 == ST_INLET) vp1 = pin_q;
-              if (sm1 == ST_FLUID) vm1 = (R)sin_[q * N + nb_index(d, -1)];
-              else if (sm1 == ST_INLET) vm1 = pin_q;
-              R vp2, vm2;
-              if (s1 == ST_FLUID) {
-                if (s2 == ST_FLUID) vp2 = (R)sin_[q * N + nb_index(d, 2)];
-                else vp2 = s2 == ST_INLET ? pin_q : vp1;
-              } else {
-                vp2 = s1 == ST_SOLID ? vm1 : s1 == ST_INLET ? pin_q : v0;
-              }
-              if (sm1 == ST_FLUID) {
-                if (sm2 == ST_FLUID) vm2 = (R)sin_[q * N + nb_index(d, -2)];
-                else vm2 = sm2 == ST_INLET ? pin_q : vm1;
-              } else {
-                vm2 = sm1 == ST_SOLID ? vp1 : sm1 == ST_INLET ? pin_q : v0;
-              }
-              R D_;
-              if (u[d] >= R(0))
-                D_ = weno3_face(vm1, v0, vp1, eps) - weno3_face(vm2, vm1, v0, eps);
-              else
-                D_ = weno3_face(vp2, vp1, v0, eps) - weno3_face(vp1, v0, vm1, eps);
-              adv += u[d] * D_;
-            }
-            const R nv = phi0[q] + (R_s[q] - adv);
-            bad |= !isfinite(nv);
-            sout[q * N + n] = (Sc)nv;
-          }
+        for (int q = 0; q < NS; ++q) {
+          const R nv = phi0[q] + (R_s[q] - adv[q]);
+          bad |= !isfinite(nv);
+          stg(sout + (size_t)q * N, un, (Sc)nv);
         }
-      }
-
-      // ---------------------------------------------------------------- collision
-      if (!EXTRACT) {
-        const R r = R(a.th.rho_ref) / rho0;             // P0/(rho cs2)
-        R Xi[Q];
-        R e[Q];
-        R Es = R(0), Xs = R(0);
+        // ------------------------------------------------------------ collision
+        const R r = fdiv(a.th.rho_ref, rho0);           // P0/(rho cs2)
         const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const R ugr = u[0] * gradrho[0] + u[1] * gradrho[1] + u[2] * gradrho[2];
-        const R half_rcs = R(0.5) / (rho0 * s);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
+        const R rsL = rho0 * s * Lam;
+        // Eq. 2: Xi_i = cs2 (f_eq/rho - w)(c - u).grad rho + w rho cs2 Lambda (recomputed
+        // where needed rather than held in registers across the collision)
+        auto xi_of = [&](int i) -> R {
           if constexpr (NS >= 2) {
             const R cu = R(cx(i)) * u[0] + R(cy(i)) * u[1] + (D == 3 ? R(cz(i)) * u[2] : R(0));
             const R cg = R(cx(i)) * gradrho[0] + R(cy(i)) * gradrho[1] + (D == 3 ? R(cz(i)) * gradrho[2] : R(0));
             const R wi = R(wgt<Q>(i));
-            // Eq. 2: cs2 (f_eq/rho - w)(c - u).grad rho + w rho cs2 Lambda
-            Xi[i] = s * wi * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu) * (cg - ugr) + wi * rho0 * s * Lam;
+            return s * wi * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu) * (cg - ugr) + wi * rsL;
           } else {
-            Xi[i] = R(0);
+            return R(0);
           }
-          e[i] = r * gh[i] + Xi[i] * half_rcs;           // Eq. 13 minus the weights
+        };
+        R e[Q];
+        R Es = R(0), Xs = R(0);
+        const R half_rcs = fdiv(R(0.5), rho0 * s);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const R xi = xi_of(i);
+          e[i] = r * gh[i] + xi * half_rcs;              // Eq. 13 minus the weights
           Es += e[i];
-          Xs += Xi[i];
+          Xs += xi;
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) e[i] -= R(wgt<Q>(i)) * Es;   // d = f~ - w
         const R nu = viscosity(a.th, rho0);
         Rates<R> rt;
         rt.tau0 = nu / s + R(0.5);
-        rt.smag18 = R(a.smag18);
-        rt.wb = R(a.wb);
-        rt.wh = R(a.wh);
-        const R base = sg + Xs * R(0.5) / P0;             // (1/r) m0 - 1
-        const R invr = rho0 / R(a.th.rho_ref);
+        rt.smag18 = a.smag18;
+        rt.wb = a.wb;
+        rt.wh = a.wh;
+        const R hP0 = R(0.5) * a.invP0;
+        const R base = sg + Xs * hP0;                    // (1/r) m0 - 1
+        const R invr = fdiv(rho0, a.th.rho_ref);
         if (a.collision == 0) {
           if constexpr (Q == 9) collide_d2q9(e, u[0], u[1], rt);
           else collide_d3q27(e, u[0], u[1], u[2], rt);
 #pragma unroll
           for (int i = 0; i < Q; ++i) {
-            const R gs = R(wgt<Q>(i)) * base + e[i] * invr + Xi[i] * R(0.5) / P0;   // Eq. 8
-            pout[i * N + n] = encode<St>(gs);
+            const R gs = R(wgt<Q>(i)) * base + e[i] * invr + xi_of(i) * hP0;   // Eq. 8
+            stg(pout + (size_t)i * N, un, encode<St>(gs));
           }
         } else {
           // BGK in the pre-conditioned frame (Eq. 5 with the half-source split)
           const R om = shear_rate(rt, pipi_of<Q, R>(e, u));
-          const R ph1 = Ph / P0 - R(1);
-          const R kq = rho0 * s / P0;
+          const R ph1 = Ph * a.invP0 - R(1);
+          const R kq = rho0 * s * a.invP0;
 #pragma unroll
           for (int i = 0; i < Q; ++i) {
             const R cu = R(cx(i)) * u[0] + R(cy(i)) * u[1] + (D == 3 ? R(cz(i)) * u[2] : R(0));
             const R geq = R(wgt<Q>(i)) * (ph1 + kq * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
-            const R xh = Xi[i] * R(0.5) / P0;
+            const R xh = xi_of(i) * hP0;
             const R gp = gh[i] + xh;
-            pout[i * N + n] = encode<St>(gp - om * (gp - geq) + xh);
+            stg(pout + (size_t)i * N, un, encode<St>(gp - om * (gp - geq) + xh));
           }
         }
         bad |= !isfinite(Ph + u[0] + u[1] + u[2]);
@@ -488,37 +583,45 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
       red[4] = rd * (double)u[2];
       red[5] = 0.5 * rd * ((double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]);
       if constexpr (NS <= 1) {
-        red[6] = 1.0 / a.th.T_ref;
+        red[6] = a.inv_T_ref_d;
       } else if constexpr (NS == 2) {
         red[6] = 1.0 / (double)phi0[0];
       } else {
         double ys = 0.0, inv = 0.0;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) { ys += (double)phi0[1 + q]; inv += (double)phi0[1 + q] / a.th.chem[5 + q]; }
-        inv += (1.0 - ys) / a.th.chem[10];
+        for (int q = 0; q < 5; ++q) { ys += (double)phi0[1 + q]; inv += (double)phi0[1 + q] / a.W_d[q]; }
+        inv += (1.0 - ys) / a.W_d[5];
         red[6] = 1.0 / (inv * (double)phi0[0]);
       }
       if constexpr (NS >= 2) red[7] = rd * (double)phi0[1];
     }
   }
-  block_sums(red, a.partials + (long long)tile * 8);
+  block_sums(red, a.partials + (size_t)tile * 8);
 }
 
-// Deterministic second pass: one block sums the per-block records in a fixed order.
-static __global__ __launch_bounds__(256) void finalize_sums(const double *partials, int nblocks, double *out) {
-  __shared__ double sh[256];
-  for (int k = 0; k < 8; ++k) {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += 256) acc += partials[(long long)b * 8 + k];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = sh[0];
+
+// Deterministic reduction of the per-block records: stage 1 gives each of up to 256
+// blocks a contiguous range of records, stage 2 sums the stage-1 records in one block.
+// The order of every addition is fixed by the launch shape, so results are bitwise
+// repeatable.
+static __global__ __launch_bounds__(256) void finalize_stage(const double *in, int nrec, int chunk, double *out) {
+  __shared__ double sh[8][256];
+  const int b0 = blockIdx.x * chunk;
+  const int b1 = min(nrec, b0 + chunk);
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += 256)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] += in[(size_t)b * 8 + k];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
     __syncthreads();
   }
+  if (threadIdx.x < 8) out[(size_t)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // Geometry words from a solid mask (see GeomWord).
@@ -559,7 +662,7 @@ __global__ __launch_bounds__(256) void geometry_kernel(const uint8_t *solid, voi
 
 // Equilibrium initialisation (Eq. 6) from FP64 fields; populations stored as deviations.
 template <int Q, int PREC, int NS>
-__global__ __launch_bounds__(256) void init_kernel(StepArgs a, const double *Ph, const double *u,
+__global__ __launch_bounds__(256) void init_kernel(KArgs<double> a, const double *Ph, const double *u,
                                                    const double *scal) {
   using P = Prec<PREC>;
   using St = typename P::St;

@@ -40,6 +40,8 @@ def _params(lat, shape, phys, coll, faces=None, **kw):
     elif phys == "one_step":
         p["inlet_T"] = 300.0
         p["inlet_Y"] = [1.0] + [0.0] * 7
+    elif phys == "passive":
+        p["inlet_T"] = 0.5
     return p
 
 
@@ -113,3 +115,33 @@ def test_taylor_green_64_horizon():
     assert torch.allclose(f["u"].cpu(), u_o, atol=1e-13, rtol=0)
     assert torch.allclose(f["P_h"].cpu(), P_o, atol=1e-13, rtol=0)
     assert np.allclose(f["sums"], sums_o.numpy(), rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 13, 70)), ("D3Q27", (7, 6, 9))])
+@pytest.mark.parametrize("phys", ["isothermal", "passive", "one_step", "two_step"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
+def test_reduced_precision_one_step(lat, shape, phys, prec):
+    """FP32 math (FP32 or FP16 storage) against the FP64 oracle on inputs rounded to the
+    storage precision.  FP32: 2e-7 absolute in ghat (deviations ~1e-2, a few hundred
+    single-precision operations of relative error 6e-8 on values of that size) and 2e-6 of
+    max(range, |value|) per scalar.  FP16 storage: the GPU output is rounded to half precision, so
+    the bound is half an FP16 ulp of the value (2^-11 |ghat|) plus the FP32 bound."""
+    faces = ["inlet", "outlet", "periodic", "periodic", "wall", "wall"] if lat == "D3Q27" else \
+        ["wall", "outlet", "periodic", "periodic", "periodic", "periodic"]
+    p = _params(lat, shape, phys, "cumulant", faces=faces, precision=prec,
+                inlet_u=[0.03, 0.0, 0.0], inlet_noise=0.05)
+    ghat, scal = random_state(p, 21)
+    s = make_solver(p)
+    gpu_state(s, ghat, scal)
+    s.step(1)
+    g_pops, g_scal, _ = fetch(s)
+    st, _ = OS.step(p, oracle_state(p, ghat, scal))
+    o_pops = oracle_ghat(p, st)
+    tol = 2e-7 + (np.abs(o_pops) * 2.0 ** -11 if prec == "fp16s" else 0.0)
+    assert (np.abs(g_pops - o_pops) <= tol).all(), np.abs(g_pops - o_pops).max()
+    if scal.shape[0]:
+        o = st["scal"].numpy()
+        scale = np.maximum(np.array(p["weno_scale"][:scal.shape[0]]).reshape(-1, 1, 1, 1), np.abs(o))
+        err = (np.abs(g_scal - o) / scale).max()
+        assert err <= 2e-6, err
+    s.close()
