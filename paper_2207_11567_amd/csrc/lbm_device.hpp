@@ -59,18 +59,23 @@ __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_a
 // Central moments of orders 0,1,2 about u of a 3-point distribution on {-1,0,+1}
 // (Geier et al. 2015, the 1-D factor of the D2Q9/D3Q27 moment transform), in place.
 template <class R> __device__ __forceinline__ void fwd3(R &m, R &z, R &p, R u) {
-  const R k0 = m + z + p;
-  const R d = p - m;
+  // k0 = m + z + p, k1 = (p - m) - u k0, k2 = (p + m) - 2u (p - m) + u^2 k0
+  //                                      = (p + m) - u ((p - m) + k1)
+  const R sp = p + m, d = p - m;
+  const R k0 = sp + z;
   const R k1 = d - u * k0;
-  const R k2 = (p + m) - R(2) * u * d + u * u * k0;
+  const R k2 = sp - u * (d + k1);
   m = k0; z = k1; p = k2;
 }
 template <class R> __device__ __forceinline__ void inv3(R &k0, R &k1, R &k2, R u) {
-  const R a = k0, b = k1, c = k2;
-  const R uu = u * u;
-  const R zero = a * (R(1) - uu) - R(2) * u * b - c;
-  const R plus = R(0.5) * (a * (uu + u) + b * (R(2) * u + R(1)) + c);
-  const R minus = R(0.5) * (a * (uu - u) + b * (R(2) * u - R(1)) + c);
+  // raw moments m1 = k1 + u k0, m2 = k2 + 2u k1 + u^2 k0 = k2 + u (k1 + m1);
+  // populations f0 = k0 - m2, f+ = (m2 + m1)/2, f- = (m2 - m1)/2
+  const R m1 = k1 + u * k0;
+  const R m2 = k2 + u * (k1 + m1);
+  const R h1 = R(0.5) * m1;
+  const R zero = k0 - m2;
+  const R plus = R(0.5) * m2 + h1;
+  const R minus = R(0.5) * m2 - h1;
   k0 = minus; k1 = zero; k2 = plus;
 }
 
@@ -134,7 +139,9 @@ __device__ __forceinline__ R collide_d2q9(R (&d)[9], R ux, R uy, const Rates<R> 
   return om;
 }
 
-template <class R>
+// HIGH1: every cumulant of order >= 3 relaxes with rate one, i.e. is set to its
+// equilibrium 0; the pre-collision higher-order cumulants are then not needed.
+template <class R, bool HIGH1>
 __device__ __forceinline__ R collide_d3q27(R (&d)[27], R ux, R uy, R uz, const Rates<R> &rt) {
   constexpr R s = R(1.0 / 3.0);
   // forward sweeps z (stride 9), y (stride 3), x (stride 1); kappa^d_abc at d[a+3b+9c]
@@ -153,28 +160,36 @@ __device__ __forceinline__ R collide_d3q27(R (&d)[27], R ux, R uy, R uz, const R
   // second order (diagonal shifted by cs2)
   const R A = ux2 + KD(2, 0, 0), B = uy2 + KD(0, 2, 0), C = uz2 + KD(0, 0, 2);
   const R k110 = ux * uy + KD(1, 1, 0), k101 = ux * uz + KD(1, 0, 1), k011 = uy * uz + KD(0, 1, 1);
-  // third order: kappa = kappa^w + kappa^d
-  const R k210 = KD(2, 1, 0) - Kx2 * uy, k201 = KD(2, 0, 1) - Kx2 * uz;
-  const R k120 = KD(1, 2, 0) - ux * Ky2, k021 = KD(0, 2, 1) - Ky2 * uz;
-  const R k102 = KD(1, 0, 2) - ux * Kz2, k012 = KD(0, 1, 2) - uy * Kz2;
-  const R k111 = KD(1, 1, 1) - ux * uy * uz;
-  // fourth order cumulants
-  const R c211 = KD(2, 1, 1) - s * KD(0, 1, 1) + ux2 * uy * uz - A * k011 - R(2) * k110 * k101;
-  const R c121 = KD(1, 2, 1) - s * KD(1, 0, 1) + uy2 * ux * uz - B * k101 - R(2) * k110 * k011;
-  const R c112 = KD(1, 1, 2) - s * KD(1, 1, 0) + uz2 * ux * uy - C * k110 - R(2) * k101 * k011;
-  const R c220 = KD(2, 2, 0) - s * (KD(2, 0, 0) + KD(0, 2, 0)) + ux2 * uy2 - A * B - R(2) * k110 * k110;
-  const R c202 = KD(2, 0, 2) - s * (KD(2, 0, 0) + KD(0, 0, 2)) + ux2 * uz2 - A * C - R(2) * k101 * k101;
-  const R c022 = KD(0, 2, 2) - s * (KD(0, 2, 0) + KD(0, 0, 2)) + uy2 * uz2 - B * C - R(2) * k011 * k011;
-  // fifth order cumulants
+  // third order: kappa = kappa^w + kappa^d (unused when they all relax to zero)
+  R k210 = R(0), k201 = R(0), k120 = R(0), k021 = R(0), k102 = R(0), k012 = R(0), k111 = R(0);
+  R c211 = R(0), c121 = R(0), c112 = R(0), c220 = R(0), c202 = R(0), c022 = R(0);
+  R c221 = R(0), c212 = R(0), c122 = R(0), c222 = R(0);
   const R s2 = s * s;
-  const R c221 = KD(2, 2, 1) + uz * (s2 - ux2 * uy2) - s * (KD(0, 2, 1) + KD(2, 0, 1)) - A * k021 -
+  if constexpr (!HIGH1) {
+  // third order: kappa = kappa^w + kappa^d
+    k210 = KD(2, 1, 0) - Kx2 * uy;
+    k201 = KD(2, 0, 1) - Kx2 * uz;
+    k120 = KD(1, 2, 0) - ux * Ky2;
+    k021 = KD(0, 2, 1) - Ky2 * uz;
+    k102 = KD(1, 0, 2) - ux * Kz2;
+    k012 = KD(0, 1, 2) - uy * Kz2;
+    k111 = KD(1, 1, 1) - ux * uy * uz;
+    // fourth order cumulants
+    c211 = KD(2, 1, 1) - s * KD(0, 1, 1) + ux2 * uy * uz - A * k011 - R(2) * k110 * k101;
+    c121 = KD(1, 2, 1) - s * KD(1, 0, 1) + uy2 * ux * uz - B * k101 - R(2) * k110 * k011;
+    c112 = KD(1, 1, 2) - s * KD(1, 1, 0) + uz2 * ux * uy - C * k110 - R(2) * k101 * k011;
+    c220 = KD(2, 2, 0) - s * (KD(2, 0, 0) + KD(0, 2, 0)) + ux2 * uy2 - A * B - R(2) * k110 * k110;
+    c202 = KD(2, 0, 2) - s * (KD(2, 0, 0) + KD(0, 0, 2)) + ux2 * uz2 - A * C - R(2) * k101 * k101;
+    c022 = KD(0, 2, 2) - s * (KD(0, 2, 0) + KD(0, 0, 2)) + uy2 * uz2 - B * C - R(2) * k011 * k011;
+    // fifth order cumulants
+    c221 = KD(2, 2, 1) + uz * (s2 - ux2 * uy2) - s * (KD(0, 2, 1) + KD(2, 0, 1)) - A * k021 -
                  B * k201 - R(4) * k110 * k111 - R(2) * (k101 * k120 + k011 * k210);
-  const R c212 = KD(2, 1, 2) + uy * (s2 - ux2 * uz2) - s * (KD(0, 1, 2) + KD(2, 1, 0)) - A * k012 -
+    c212 = KD(2, 1, 2) + uy * (s2 - ux2 * uz2) - s * (KD(0, 1, 2) + KD(2, 1, 0)) - A * k012 -
                  C * k210 - R(4) * k101 * k111 - R(2) * (k110 * k102 + k011 * k201);
-  const R c122 = KD(1, 2, 2) + ux * (s2 - uy2 * uz2) - s * (KD(1, 0, 2) + KD(1, 2, 0)) - B * k102 -
+    c122 = KD(1, 2, 2) + ux * (s2 - uy2 * uz2) - s * (KD(1, 0, 2) + KD(1, 2, 0)) - B * k102 -
                  C * k120 - R(4) * k011 * k111 - R(2) * (k110 * k012 + k101 * k021);
-  // sixth order cumulant
-  const R c222 = KD(2, 2, 2) - s2 * (KD(2, 0, 0) + KD(0, 2, 0) + KD(0, 0, 2)) +
+    // sixth order cumulant
+    c222 = KD(2, 2, 2) - s2 * (KD(2, 0, 0) + KD(0, 2, 0) + KD(0, 0, 2)) +
                  s * (ux2 * uy2 + uy2 * uz2 + uz2 * ux2 - A * B - B * C - C * A) +
                  ux2 * uy2 * uz2 - A * B * C - (s + A) * c022 - (s + B) * c202 - (s + C) * c220 -
                  R(4) * (k110 * c112 + k101 * c121 + k011 * c211) - R(4) * k111 * k111 -
@@ -182,9 +197,10 @@ __device__ __forceinline__ R collide_d3q27(R (&d)[27], R ux, R uy, R uz, const R
                  R(2) * ((s + A) * k011 * k011 + (s + B) * k101 * k101 + (s + C) * k110 * k110) -
                  R(8) * k110 * k101 * k011;
 
+  }
   const R om = shear_rate(rt, A * A + B * B + C * C + R(2) * (k110 * k110 + k101 * k101 + k011 * k011));
   // relaxation towards the cumulant equilibria
-  const R o1 = R(1) - om, h = R(1) - rt.wh;
+  const R o1 = R(1) - om, h = HIGH1 ? R(0) : R(1) - rt.wh;
   const R Dxy = o1 * (A - B), Dxz = o1 * (A - C);
   const R Tr = (R(1) - rt.wb) * (A + B + C);
   const R As = (Tr + Dxy + Dxz) * R(1.0 / 3.0);
@@ -203,32 +219,57 @@ __device__ __forceinline__ R collide_d3q27(R (&d)[27], R ux, R uy, R uz, const R
   KD(1, 1, 0) = q110 - ux * uy;
   KD(1, 0, 1) = q101 - ux * uz;
   KD(0, 1, 1) = q011 - uy * uz;
-  KD(2, 1, 0) = q210 + Kx2 * uy;
-  KD(2, 0, 1) = q201 + Kx2 * uz;
-  KD(1, 2, 0) = q120 + ux * Ky2;
-  KD(0, 2, 1) = q021 + Ky2 * uz;
-  KD(1, 0, 2) = q102 + ux * Kz2;
-  KD(0, 1, 2) = q012 + uy * Kz2;
-  KD(1, 1, 1) = q111 + ux * uy * uz;
-  KD(2, 1, 1) = q211 + s * (q011 - uy * uz) + As * q011 - ux2 * uy * uz + R(2) * q110 * q101;
-  KD(1, 2, 1) = q121 + s * (q101 - ux * uz) + Bs * q101 - uy2 * ux * uz + R(2) * q110 * q011;
-  KD(1, 1, 2) = q112 + s * (q110 - ux * uy) + Cs * q110 - uz2 * ux * uy + R(2) * q101 * q011;
-  KD(2, 2, 0) = q220 + s * (As - ux2 + Bs - uy2) + As * Bs - ux2 * uy2 + R(2) * q110 * q110;
-  KD(2, 0, 2) = q202 + s * (As - ux2 + Cs - uz2) + As * Cs - ux2 * uz2 + R(2) * q101 * q101;
-  KD(0, 2, 2) = q022 + s * (Bs - uy2 + Cs - uz2) + Bs * Cs - uy2 * uz2 + R(2) * q011 * q011;
-  KD(2, 2, 1) = q221 + (s + As) * q021 + (s + Bs) * q201 + R(4) * q110 * q111 +
-                R(2) * (q101 * q120 + q011 * q210) + uz * Kx2 * Ky2;
-  KD(2, 1, 2) = q212 + (s + As) * q012 + (s + Cs) * q210 + R(4) * q101 * q111 +
-                R(2) * (q110 * q102 + q011 * q201) + uy * Kx2 * Kz2;
-  KD(1, 2, 2) = q122 + (s + Bs) * q102 + (s + Cs) * q120 + R(4) * q011 * q111 +
-                R(2) * (q110 * q012 + q101 * q021) + ux * Ky2 * Kz2;
-  KD(2, 2, 2) = q222 + s2 * (As - ux2 + Bs - uy2 + Cs - uz2) +
-                s * (As * Bs + Bs * Cs + Cs * As - ux2 * uy2 - uy2 * uz2 - uz2 * ux2) +
-                As * Bs * Cs - ux2 * uy2 * uz2 + (s + As) * q022 + (s + Bs) * q202 + (s + Cs) * q220 +
-                R(4) * (q110 * q112 + q101 * q121 + q011 * q211) + R(4) * q111 * q111 +
-                R(2) * (q210 * q012 + q201 * q021 + q120 * q102) +
-                R(2) * ((s + As) * q011 * q011 + (s + Bs) * q101 * q101 + (s + Cs) * q110 * q110) +
-                R(8) * q110 * q101 * q011;
+  if constexpr (HIGH1) {
+    // all post-collision cumulants of order >= 3 vanish
+    KD(2, 1, 0) = Kx2 * uy;
+    KD(2, 0, 1) = Kx2 * uz;
+    KD(1, 2, 0) = ux * Ky2;
+    KD(0, 2, 1) = Ky2 * uz;
+    KD(1, 0, 2) = ux * Kz2;
+    KD(0, 1, 2) = uy * Kz2;
+    KD(1, 1, 1) = ux * uy * uz;
+    KD(2, 1, 1) = s * (q011 - uy * uz) + As * q011 - ux2 * uy * uz + R(2) * q110 * q101;
+    KD(1, 2, 1) = s * (q101 - ux * uz) + Bs * q101 - uy2 * ux * uz + R(2) * q110 * q011;
+    KD(1, 1, 2) = s * (q110 - ux * uy) + Cs * q110 - uz2 * ux * uy + R(2) * q101 * q011;
+    KD(2, 2, 0) = s * (As - ux2 + Bs - uy2) + As * Bs - ux2 * uy2 + R(2) * q110 * q110;
+    KD(2, 0, 2) = s * (As - ux2 + Cs - uz2) + As * Cs - ux2 * uz2 + R(2) * q101 * q101;
+    KD(0, 2, 2) = s * (Bs - uy2 + Cs - uz2) + Bs * Cs - uy2 * uz2 + R(2) * q011 * q011;
+    KD(2, 2, 1) = uz * Kx2 * Ky2;
+    KD(2, 1, 2) = uy * Kx2 * Kz2;
+    KD(1, 2, 2) = ux * Ky2 * Kz2;
+    KD(2, 2, 2) = s2 * (As - ux2 + Bs - uy2 + Cs - uz2) +
+                  s * (As * Bs + Bs * Cs + Cs * As - ux2 * uy2 - uy2 * uz2 - uz2 * ux2) +
+                  As * Bs * Cs - ux2 * uy2 * uz2 +
+                  R(2) * ((s + As) * q011 * q011 + (s + Bs) * q101 * q101 + (s + Cs) * q110 * q110) +
+                  R(8) * q110 * q101 * q011;
+  } else {
+    KD(2, 1, 0) = q210 + Kx2 * uy;
+    KD(2, 0, 1) = q201 + Kx2 * uz;
+    KD(1, 2, 0) = q120 + ux * Ky2;
+    KD(0, 2, 1) = q021 + Ky2 * uz;
+    KD(1, 0, 2) = q102 + ux * Kz2;
+    KD(0, 1, 2) = q012 + uy * Kz2;
+    KD(1, 1, 1) = q111 + ux * uy * uz;
+    KD(2, 1, 1) = q211 + s * (q011 - uy * uz) + As * q011 - ux2 * uy * uz + R(2) * q110 * q101;
+    KD(1, 2, 1) = q121 + s * (q101 - ux * uz) + Bs * q101 - uy2 * ux * uz + R(2) * q110 * q011;
+    KD(1, 1, 2) = q112 + s * (q110 - ux * uy) + Cs * q110 - uz2 * ux * uy + R(2) * q101 * q011;
+    KD(2, 2, 0) = q220 + s * (As - ux2 + Bs - uy2) + As * Bs - ux2 * uy2 + R(2) * q110 * q110;
+    KD(2, 0, 2) = q202 + s * (As - ux2 + Cs - uz2) + As * Cs - ux2 * uz2 + R(2) * q101 * q101;
+    KD(0, 2, 2) = q022 + s * (Bs - uy2 + Cs - uz2) + Bs * Cs - uy2 * uz2 + R(2) * q011 * q011;
+    KD(2, 2, 1) = q221 + (s + As) * q021 + (s + Bs) * q201 + R(4) * q110 * q111 +
+                  R(2) * (q101 * q120 + q011 * q210) + uz * Kx2 * Ky2;
+    KD(2, 1, 2) = q212 + (s + As) * q012 + (s + Cs) * q210 + R(4) * q101 * q111 +
+                  R(2) * (q110 * q102 + q011 * q201) + uy * Kx2 * Kz2;
+    KD(1, 2, 2) = q122 + (s + Bs) * q102 + (s + Cs) * q120 + R(4) * q011 * q111 +
+                  R(2) * (q110 * q012 + q101 * q021) + ux * Ky2 * Kz2;
+    KD(2, 2, 2) = q222 + s2 * (As - ux2 + Bs - uy2 + Cs - uz2) +
+                  s * (As * Bs + Bs * Cs + Cs * As - ux2 * uy2 - uy2 * uz2 - uz2 * ux2) +
+                  As * Bs * Cs - ux2 * uy2 * uz2 + (s + As) * q022 + (s + Bs) * q202 + (s + Cs) * q220 +
+                  R(4) * (q110 * q112 + q101 * q121 + q011 * q211) + R(4) * q111 * q111 +
+                  R(2) * (q210 * q012 + q201 * q021 + q120 * q102) +
+                  R(2) * ((s + As) * q011 * q011 + (s + Bs) * q101 * q101 + (s + Cs) * q110 * q110) +
+                  R(8) * q110 * q101 * q011;
+  }
 #undef KD
   // inverse sweeps x, y, z
 #pragma unroll
@@ -305,12 +346,27 @@ template <class R> __device__ __forceinline__ R viscosity(const ThermoT<R> &t, R
   return t.const_mu ? fdiv(t.mu_ref, rho) : t.nu_ref;
 }
 
-// Jiang-Shu WENO3 face value between b and c from the upwind-biased triple (a, b, c).
+// Jiang-Shu WENO3 face value between b and c from the upwind-biased triple (a, b, c):
+// candidates -a/2 + 3b/2 and (b + c)/2 with linear weights 1/3, 2/3, smoothness
+// (b-a)^2 and (c-b)^2, alpha = d/(eps + beta)^2.
 template <class R> __device__ __forceinline__ R weno3_face(R a, R b, R c, R eps) {
   const R b0 = (b - a) * (b - a), b1 = (c - b) * (c - b);
   const R e0 = eps + b0, e1 = eps + b1;
   const R a0 = R(1.0 / 3.0) * e1 * e1, a1 = R(2.0 / 3.0) * e0 * e0;   // alpha ratios
   return fdiv(a0 * (R(-0.5) * a + R(1.5) * b) + a1 * (R(0.5) * b + R(0.5) * c), a0 + a1);
+}
+
+// Upwind WENO3 derivative across a cell from the upwind neighbours U2, U1, the cell value
+// v0 and the downwind neighbour D1: face(U1, v0, D1) - face(U2, U1, v0), with the two
+// faces sharing the difference v0 - U1.  Each face value is b + (1/2) q with
+// q = (S1 d0 + 2 S0 d1)/(S1 + 2 S0), d0 = b - a, d1 = c - b, S = (eps + d^2)^2.
+template <class R> __device__ __forceinline__ R weno3_diff(R U2, R U1, R v0, R D1, R eps) {
+  const R dA = U1 - U2, dB = v0 - U1, dC = D1 - v0;
+  const R eA = eps + dA * dA, eB = eps + dB * dB, eC = eps + dC * dC;
+  const R SA = eA * eA, SB = eB * eB, SC = eC * eC;
+  const R q1 = fdiv(SC * dB + R(2) * (SB * dC), SC + R(2) * SB);
+  const R q2 = fdiv(SB * dA + R(2) * (SA * dB), SB + R(2) * SA);
+  return dB + R(0.5) * (q1 - q2);
 }
 
 }  // namespace lbm

@@ -405,10 +405,11 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             if (FAST || sp1 == ST_FLUID) rp = density<NS, R>(a.th, vp1); else if (sp1 == ST_INLET) rp = rho_in;
             if (FAST || sm1 == ST_FLUID) rm = density<NS, R>(a.th, vm1); else if (sm1 == ST_INLET) rm = rho_in;
             gradrho[d] = R(0.5) * (rp - rm);
+            // face coefficients: arithmetic mean of rho D (uniform when rho nu is constant)
             R cfp, cfm;
             if (FAST) {
-              cfp = R(0.5) * (rhoD0 + rp * viscosity(a.th, rp) * a.th.inv_Pr);
-              cfm = R(0.5) * (rhoD0 + rm * viscosity(a.th, rm) * a.th.inv_Pr);
+              cfp = a.th.const_mu ? rhoD0 : R(0.5) * (rhoD0 + rp * viscosity(a.th, rp) * a.th.inv_Pr);
+              cfm = a.th.const_mu ? rhoD0 : R(0.5) * (rhoD0 + rm * viscosity(a.th, rm) * a.th.inv_Pr);
             } else {
               const bool fp = sp1 == ST_FLUID || sp1 == ST_INLET, fm = sm1 == ST_FLUID || sm1 == ST_INLET;
               cfp = fp ? R(0.5) * (rhoD0 + (sp1 == ST_INLET ? rhoD_in : rp * viscosity(a.th, rp) * a.th.inv_Pr)) : R(0);
@@ -439,7 +440,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
                 }
                 const R vU1 = up ? vm1[q] : vp1[q];
                 const R vD1 = up ? vp1[q] : vm1[q];
-                adv[q] += au * (weno3_face(vU1, v0, vD1, a.eps[q]) - weno3_face(vU2, vU1, v0, a.eps[q]));
+                adv[q] += au * weno3_diff(vU2, vU1, v0, vD1, a.eps[q]);
               }
             }
           }
@@ -528,14 +529,20 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           }
         };
         R e[Q];
+        R Xi[NS >= 2 ? Q : 1];
         R Es = R(0), Xs = R(0);
         const R half_rcs = fdiv(R(0.5), rho0 * s);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const R xi = xi_of(i);
-          e[i] = r * gh[i] + xi * half_rcs;              // Eq. 13 minus the weights
+          if constexpr (NS >= 2) {
+            const R xi = xi_of(i);
+            Xi[i] = xi;
+            e[i] = r * gh[i] + xi * half_rcs;            // Eq. 13 minus the weights
+            Xs += xi;
+          } else {
+            e[i] = gh[i];                                // rho = rho_ref, Xi = 0
+          }
           Es += e[i];
-          Xs += xi;
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) e[i] -= R(wgt<Q>(i)) * Es;   // d = f~ - w
@@ -550,10 +557,13 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
         const R invr = fdiv(rho0, a.th.rho_ref);
         if (a.collision == 0) {
           if constexpr (Q == 9) collide_d2q9(e, u[0], u[1], rt);
-          else collide_d3q27(e, u[0], u[1], u[2], rt);
+          else if (a.wh == R(1)) collide_d3q27<R, true>(e, u[0], u[1], u[2], rt);
+          else collide_d3q27<R, false>(e, u[0], u[1], u[2], rt);
 #pragma unroll
           for (int i = 0; i < Q; ++i) {
-            const R gs = R(wgt<Q>(i)) * base + e[i] * invr + xi_of(i) * hP0;   // Eq. 8
+            R gs;
+            if constexpr (NS >= 2) gs = R(wgt<Q>(i)) * base + e[i] * invr + Xi[i] * hP0;   // Eq. 8
+            else gs = R(wgt<Q>(i)) * base + e[i];
             stg(pout + (size_t)i * N, un, encode<St>(gs));
           }
         } else {
@@ -565,7 +575,8 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           for (int i = 0; i < Q; ++i) {
             const R cu = R(cx(i)) * u[0] + R(cy(i)) * u[1] + (D == 3 ? R(cz(i)) * u[2] : R(0));
             const R geq = R(wgt<Q>(i)) * (ph1 + kq * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
-            const R xh = xi_of(i) * hP0;
+            R xh = R(0);
+            if constexpr (NS >= 2) xh = Xi[i] * hP0;
             const R gp = gh[i] + xh;
             stg(pout + (size_t)i * N, un, encode<St>(gp - om * (gp - geq) + xh));
           }
@@ -585,13 +596,13 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
       if constexpr (NS <= 1) {
         red[6] = a.inv_T_ref_d;
       } else if constexpr (NS == 2) {
-        red[6] = 1.0 / (double)phi0[0];
+        red[6] = (double)fdiv(R(1), phi0[0]);
       } else {
-        double ys = 0.0, inv = 0.0;
+        R ys = R(0), inv = R(0);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) { ys += (double)phi0[1 + q]; inv += (double)phi0[1 + q] / a.W_d[q]; }
-        inv += (1.0 - ys) / a.W_d[5];
-        red[6] = 1.0 / (inv * (double)phi0[0]);
+        for (int q = 0; q < 5; ++q) { ys += phi0[1 + q]; inv += phi0[1 + q] * a.th.inv_W[q]; }
+        inv += (R(1) - ys) * a.th.inv_W[5];
+        red[6] = (double)fdiv(R(1), inv * phi0[0]);
       }
       if constexpr (NS >= 2) red[7] = rd * (double)phi0[1];
     }
