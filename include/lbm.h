@@ -132,6 +132,41 @@ lbm_status lbm_get_state(lbm_solver *s, void *pops_dst, void *scal_dst, int64_t 
 lbm_status lbm_set_state(lbm_solver *s, const void *pops_src, const void *scal_src,
                          int64_t step);
 
+/* ------------------------------------------------------------------ differentiation
+ * Discrete adjoint of one time step (reverse-mode vector-Jacobian product of the exact
+ * discrete step: collision, Smagorinsky shear rate, WENO3 advection with its nonlinear
+ * weights, centred diffusion, streaming).  Scope: D3Q27, periodic faces, no solid cells,
+ * LBM_ISOTHERMAL or LBM_PASSIVE, LBM_CUMULANT with omega_high == 1, LBM_FP64 or LBM_FP32;
+ * anything else returns LBM_E_UNSUPPORTED.  Adjoint arrays are in the compute precision
+ * (FP64 or FP32), laid out like the state: populations [27][N], scalars [S][N].
+ * At the upwind switch u_d = 0 the derivative of |u_d| is taken as +1. */
+
+/* Byte sizes of one adjoint population array, one adjoint scalar array, and the scratch
+ * buffer lbm_adjoint_step needs. */
+lbm_status lbm_adjoint_sizes(lbm_solver *s, size_t *adj_pop_bytes, size_t *adj_scal_bytes,
+                             size_t *adj_work_bytes);
+
+/* One reverse step: given the state at level n (populations and scalars in the storage
+ * format, as lbm_get_state returns them) and the adjoint of the state at level n+1,
+ * writes the adjoint of the state at level n.  In and out buffers must be distinct.
+ * Asynchronous on the stream. */
+lbm_status lbm_adjoint_step(lbm_solver *s, const void *state_pops, const void *state_scal,
+                            const void *adj_pop_in, const void *adj_scal_in, void *adj_pop_out,
+                            void *adj_scal_out, void *adj_work);
+
+/* Objective J = sum rho |u|^2 / 2 + sum (T - mean T)^2 at the given state (the second
+ * term only with a passive temperature), returned on the host in FP64, and, when
+ * adj_pop_out is not NULL, dJ/dstate written to adj_pop_out / adj_scal_out.
+ * Synchronises. */
+lbm_status lbm_objective(lbm_solver *s, const void *state_pops, const void *state_scal,
+                         double *J_host, void *adj_pop_out, void *adj_scal_out);
+
+/* Reverse of lbm_init_fields with respect to the initial velocity (and temperature):
+ * from the adjoint of the level-0 state, writes grad_u [3][N] and, if grad_scal is not
+ * NULL, grad_scal [S][N], both FP64.  u0 is the velocity given to lbm_init_fields. */
+lbm_status lbm_init_adjoint(lbm_solver *s, const void *adj_pop, const void *adj_scal,
+                            const double *u0, double *grad_u, double *grad_scal);
+
 /* Human-readable message of the last failure on this solver. */
 const char *lbm_last_error(const lbm_solver *s);
 

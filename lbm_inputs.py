@@ -100,7 +100,7 @@ def hit(n=256, k0=4.0, urms=0.05 * math.sqrt(CS2), seed=11567, nu=1e-3, cs_smag=
         comps.append((rng.standard_normal(K.shape) + 1j * rng.standard_normal(K.shape)) * amp)
     kdotu = (KX * comps[0] + KY * comps[1] + KZ * comps[2]) / K2s
     comps = [comps[0] - KX * kdotu, comps[1] - KY * kdotu, comps[2] - KZ * kdotu]
-    u = np.stack([np.fft.irfftn(c, s=(n, n, n)) for c in comps])   # axes (x, y, z)
+    u = np.stack([np.fft.irfftn(c, s=(n, n, n), axes=(0, 1, 2)) for c in comps])   # (x, y, z)
     u = u.transpose(0, 3, 2, 1).copy()                               # -> (D, z, y, x)
     u -= u.mean(axis=(1, 2, 3), keepdims=True)
     u *= urms / np.sqrt((u ** 2).mean())

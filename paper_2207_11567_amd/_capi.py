@@ -76,6 +76,11 @@ def _load():
         "lbm_step_sums": [c_void_p, P(c_double)],
         "lbm_get_state": [c_void_p, c_void_p, c_void_p, P(ctypes.c_int64)],
         "lbm_set_state": [c_void_p, c_void_p, c_void_p, ctypes.c_int64],
+        "lbm_adjoint_sizes": [c_void_p, P(c_size_t), P(c_size_t), P(c_size_t)],
+        "lbm_adjoint_step": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                             c_void_p],
+        "lbm_objective": [c_void_p, c_void_p, c_void_p, P(c_double), c_void_p, c_void_p],
+        "lbm_init_adjoint": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

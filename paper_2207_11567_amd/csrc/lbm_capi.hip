@@ -361,3 +361,103 @@ const char *lbm_last_error(const lbm_solver *s) { return s ? s->err.c_str() : g_
 void lbm_destroy(lbm_solver *s) { delete s; }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ differentiation
+static lbm_status adjoint_supported(lbm_solver *s) {
+  const lbm_params &p = s->p;
+  const char *why = nullptr;
+  if (p.lattice != LBM_D3Q27) why = "the adjoint is built for D3Q27";
+  else if (p.physics != LBM_ISOTHERMAL && p.physics != LBM_PASSIVE) why = "the adjoint covers isothermal and passive-temperature flows";
+  else if (p.collision != LBM_CUMULANT) why = "the adjoint covers the cumulant collision";
+  else if (p.omega_high != 1.0) why = "the adjoint needs omega_high == 1";
+  else if (p.precision == LBM_FP16S) why = "the adjoint runs in FP64 or FP32";
+  else if (s->has_geom) why = "the adjoint covers domains without solid cells";
+  else
+    for (int f = 0; f < 6; ++f)
+      if (p.face_bc[f] != LBM_PERIODIC) why = "the adjoint covers periodic domains";
+  if (why) {
+    s->err = why;
+    return LBM_E_UNSUPPORTED;
+  }
+  return LBM_OK;
+}
+
+extern "C" {
+
+lbm_status lbm_adjoint_sizes(lbm_solver *s, size_t *adj_pop_bytes, size_t *adj_scal_bytes, size_t *adj_work_bytes) {
+  if (!s) return LBM_E_INVALID;
+  lbm_status st = adjoint_supported(s);
+  if (st != LBM_OK) return st;
+  const size_t r = s->prec == LBM_FP64 ? 8 : 4;
+  if (adj_pop_bytes) *adj_pop_bytes = (size_t)s->Q * s->N * r;
+  if (adj_scal_bytes) *adj_scal_bytes = (size_t)s->NS * s->N * r;
+  if (adj_work_bytes) *adj_work_bytes = (size_t)(s->NS ? 13 : 1) * s->N * r;
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_step(lbm_solver *s, const void *state_pops, const void *state_scal, const void *adj_pop_in,
+                            const void *adj_scal_in, void *adj_pop_out, void *adj_scal_out, void *adj_work) {
+  if (!s) return LBM_E_INVALID;
+  lbm_status st = adjoint_supported(s);
+  if (st != LBM_OK) return st;
+  if (!state_pops || !adj_pop_in || !adj_pop_out || adj_pop_in == adj_pop_out ||
+      (s->NS && (!state_scal || !adj_scal_in || !adj_scal_out || !adj_work || adj_scal_in == adj_scal_out))) {
+    s->err = "adjoint step: state, distinct in/out adjoint buffers and the work buffer are required";
+    return LBM_E_INVALID;
+  }
+  StepArgs a = make_args(s);
+  a.pop_in = state_pops;
+  a.scal_in = state_scal;
+  hipError_t e = launch_adjoint(s->prec, s->NS, 0, a, s->nblocks, s->stream, adj_pop_in, adj_scal_in, adj_pop_out,
+                                adj_scal_out, adj_work, 0.0, nullptr, nullptr);
+  if (e != hipSuccess) return hip_fail(s, e, "adjoint kernels");
+  return LBM_OK;
+}
+
+lbm_status lbm_objective(lbm_solver *s, const void *state_pops, const void *state_scal, double *J_host,
+                         void *adj_pop_out, void *adj_scal_out) {
+  if (!s) return LBM_E_INVALID;
+  lbm_status st = adjoint_supported(s);
+  if (st != LBM_OK) return st;
+  if (!state_pops || (s->NS && !state_scal)) {
+    s->err = "objective: state buffers are required";
+    return LBM_E_INVALID;
+  }
+  StepArgs a = make_args(s);
+  a.pop_in = state_pops;
+  a.scal_in = state_scal;
+  hipError_t e = launch_adjoint(s->prec, s->NS, 1, a, s->nblocks, s->stream, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, 0.0, nullptr, nullptr);
+  if (e != hipSuccess) return hip_fail(s, e, "objective sums");
+  double sums[8];
+  e = launch_finalize(s->partials, s->nblocks, s->stage, s->sums, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(sums, s->sums, sizeof sums, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "objective sums");
+  const double mean_T = sums[1] / (double)s->N;
+  if (J_host) *J_host = sums[0] + (s->NS ? sums[2] - sums[1] * mean_T : 0.0);
+  if (adj_pop_out) {
+    e = launch_adjoint(s->prec, s->NS, 2, a, s->nblocks, s->stream, nullptr, nullptr, adj_pop_out, adj_scal_out,
+                       nullptr, mean_T, nullptr, nullptr);
+    if (e != hipSuccess) return hip_fail(s, e, "objective gradient");
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_init_adjoint(lbm_solver *s, const void *adj_pop, const void *adj_scal, const double *u0,
+                            double *grad_u, double *grad_scal) {
+  if (!s) return LBM_E_INVALID;
+  lbm_status st = adjoint_supported(s);
+  if (st != LBM_OK) return st;
+  if (!adj_pop || !u0 || !grad_u || (s->NS && grad_scal && !adj_scal)) {
+    s->err = "init adjoint: adjoint populations, u0 and grad_u are required";
+    return LBM_E_INVALID;
+  }
+  StepArgs a = make_args(s);
+  hipError_t e = launch_adjoint(s->prec, s->NS, 3, a, s->nblocks, s->stream, adj_pop, adj_scal, nullptr, grad_scal,
+                                nullptr, 0.0, u0, grad_u);
+  if (e != hipSuccess) return hip_fail(s, e, "init adjoint");
+  return LBM_OK;
+}
+
+}  // extern "C"

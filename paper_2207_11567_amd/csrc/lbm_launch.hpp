@@ -15,6 +15,11 @@ hipError_t launch_d3q27(int prec, int ns, int kind, const StepArgs &a, int nbloc
                         const double *Ph, const double *u, const double *scal);
 hipError_t launch_geometry(int Q, const uint8_t *solid, void *geom, int nx, int ny, int nz, long long N,
                            const int *face, hipStream_t st);
+// Adjoint launches (lbm_adjoint.hip).  kind 0: reverse step (p0 lamB, p1 lamT', p2 lamA out,
+// p3 lamT out, p4 coefficient scratch); 1/2: objective sums / gradient (p2 lamA, p3 lamT);
+// 3: reverse of the initialisation (p0 lamA, p1 lamT, u0, gu out, p3 grad T out).
+hipError_t launch_adjoint(int prec, int ns, int kind, const StepArgs &sa, int nblocks, hipStream_t st, const void *p0,
+                          const void *p1, void *p2, void *p3, void *p4, double mean_T, const double *u0, double *gu);
 hipError_t launch_finalize(const double *partials, int nblocks, double *stage, double *out, hipStream_t st);
 
 template <int Q, int PREC, int NS>

@@ -111,6 +111,50 @@ class Solver:
                                         ctypes.byref(step)))
         return pops, scal, step.value
 
+    # ---------------------------------------------------------------- differentiation
+    def adjoint_buffers(self):
+        """(adjoint populations, adjoint scalars, scratch) allocated for lbm_adjoint_step."""
+        pb, sb, wb = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        self._chk(C.lib().lbm_adjoint_sizes(self._h, ctypes.byref(pb), ctypes.byref(sb),
+                                            ctypes.byref(wb)))
+        rdt = torch.float64 if self.params["precision"] == "fp64" else torch.float32
+        dev = self.device
+        return (torch.zeros((self.Q,) + self.shape, dtype=rdt, device=dev),
+                torch.zeros((self.NS,) + self.shape, dtype=rdt, device=dev),
+                torch.empty(max(wb.value, 4), dtype=torch.uint8, device=dev))
+
+    def adjoint_step(self, state, lam_pop, lam_scal, work, out_pop=None, out_scal=None):
+        """Adjoint of the state at level n from the adjoint at n+1; state = (pops, scal)."""
+        pops, scal = state[0], state[1]
+        out_pop = torch.empty_like(lam_pop) if out_pop is None else out_pop
+        out_scal = torch.empty_like(lam_scal) if out_scal is None else out_scal
+        self._chk(C.lib().lbm_adjoint_step(self._h, _ptr(pops), _ptr(scal) if self.NS else None,
+                                           _ptr(lam_pop), _ptr(lam_scal) if self.NS else None,
+                                           _ptr(out_pop), _ptr(out_scal) if self.NS else None,
+                                           _ptr(work)))
+        return out_pop, out_scal
+
+    def objective(self, state, with_grad=True):
+        """J = sum rho|u|^2/2 + sum (T - mean T)^2 at the state, and dJ/dstate."""
+        pops, scal = state[0], state[1]
+        J = ctypes.c_double()
+        lp = ls = None
+        if with_grad:
+            lp, ls, _ = self.adjoint_buffers()
+        self._chk(C.lib().lbm_objective(self._h, _ptr(pops), _ptr(scal) if self.NS else None,
+                                        ctypes.byref(J), _ptr(lp) if with_grad else None,
+                                        _ptr(ls) if (with_grad and self.NS) else None))
+        return J.value, lp, ls
+
+    def init_adjoint(self, lam_pop, lam_scal, u0):
+        U = self._dev(u0).reshape((self.D,) + self.shape)
+        gu = torch.empty_like(U)
+        gs = torch.empty((self.NS,) + self.shape, dtype=torch.float64, device=self.device)
+        self._chk(C.lib().lbm_init_adjoint(self._h, _ptr(lam_pop), _ptr(lam_scal) if self.NS else None,
+                                           _ptr(U), _ptr(gu), _ptr(gs) if self.NS else None))
+        torch.cuda.synchronize(self.device)
+        return gu, gs
+
     def set_state(self, pops, scal=None, step=0):
         P = self._dev(pops, self.pop_dtype).reshape((self.Q,) + self.shape)
         S = self._dev(scal, self.scal_dtype).reshape((self.NS,) + self.shape) if self.NS else None

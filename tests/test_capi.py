@@ -1,0 +1,57 @@
+"""CPU tests of the C ABI: the library loads, exports every entry point that
+include/lbm.h declares, and rejects invalid parameters in its host-side validation
+(no GPU needed: no call here reaches the device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import lbm_inputs as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2207_11567_amd import _capi as C
+    if not os.path.exists(C.LIB_PATH):
+        from paper_2207_11567_amd import build
+        build.build(verbose=False)
+    return C, C.lib()
+
+
+def test_exports_every_declared_symbol():
+    C, lib = _lib()
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    names = set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", src))
+    assert len(names) >= 15
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("change,needle", [
+    ({"nu_ref": 0.0}, "nu_ref"),
+    ({"nz": 4}, "D2Q9"),
+    ({"omega_bulk": 2.5}, "omega_bulk"),
+    ({"face_bc": ["periodic", "wall", "periodic", "periodic", "periodic", "periodic"]}, "pairs"),
+    ({"physics": "passive", "nu_ref": 0.4}, "unstable"),
+])
+def test_validation_rejects(change, needle):
+    C, lib = _lib()
+    p = L.base_params("D2Q9", 16, 8, 1)
+    p.update(change)
+    sz = C.c_size_t()
+    st = lib.lbm_query_sizes(ctypes.byref(C.make_params(p)), ctypes.byref(sz), None, None)
+    assert st == C.LBM_E_INVALID
+    assert needle in lib.lbm_last_error(None).decode()
+
+
+def test_sizes_of_valid_parameters():
+    C, lib = _lib()
+    p, _, _, _ = L.reacting_box(16, 16, 32)
+    pb, sb, wb = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    assert lib.lbm_query_sizes(ctypes.byref(C.make_params(p)), ctypes.byref(pb), ctypes.byref(sb),
+                               ctypes.byref(wb)) == C.LBM_OK
+    N = 16 * 16 * 32
+    assert pb.value == 27 * N * 4 and sb.value == 6 * N * 4
+    assert wb.value >= N * 8 + (N // 256) * 64

@@ -1,0 +1,136 @@
+"""GPU tests of the hand-written adjoint (differentiation of the hybrid step).
+
+* per-step dot-product test in FP64: <J v, w> from central differences of the GPU step
+  against <v, J^T w> from lbm_adjoint_step (agreement to 1e-7: finite-difference
+  truncation ~eps^2 and rounding ~1e-16/eps with eps = 1e-6);
+* full gradient of a short rollout against torch autograd through the FP64 oracle on a
+  small periodic box (relative L2 1e-9);
+* FP32 rollout with segment checkpointing against central finite differences of J along
+  random directions (J summed in FP64; 2e-2 relative, the FP32 rounding of 60 steps)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as L
+from oracle import step as OS
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(n, prec="fp64", passive=True, cs=0.17):
+    p = L.base_params("D3Q27", n, n, n, nu_ref=0.01, cs_smag=cs, precision=prec,
+                      omega_bulk=1.0, omega_high=1.0)
+    if passive:
+        p.update(physics="passive", prandtl=0.7, thickening=1.5, weno_scale=[1.0] * 8)
+    return p
+
+
+def _fields(n, seed=3):
+    _, P, u = L.hit(n, seed=seed, urms=0.04)
+    T = L.passive_field(n, seed=seed + 1)[None]
+    return P, u, T
+
+
+def test_adjoint_dot_product_fp64():
+    from paper_2207_11567_amd import Solver
+    n = 12
+    p = _params(n)
+    s = Solver(p)
+    rng = np.random.default_rng(0)
+    ghat = L.random_deviation(27, (n, n, n), 7, amp=0.01)
+    T = L.passive_field(n, seed=9)[None]
+    x = (torch.from_numpy(ghat).cuda(), torch.from_numpy(T).cuda())
+    v = (torch.from_numpy(rng.standard_normal(ghat.shape) * 0.01).cuda(),
+         torch.from_numpy(rng.standard_normal(T.shape)).cuda())
+    w = (torch.from_numpy(rng.standard_normal(ghat.shape)).cuda(),
+         torch.from_numpy(rng.standard_normal(T.shape)).cuda())
+
+    def F(xg, xT):
+        s.set_state(xg, xT, 0)
+        s.step(1)
+        g2, T2, _ = s.get_state()
+        return g2.double(), T2.double()
+
+    eps = 1e-6
+    fp = F(x[0] + eps * v[0], x[1] + eps * v[1])
+    fm = F(x[0] - eps * v[0], x[1] - eps * v[1])
+    jv = ((fp[0] - fm[0]) / (2 * eps), (fp[1] - fm[1]) / (2 * eps))
+    lhs = float((jv[0] * w[0]).sum() + (jv[1] * w[1]).sum())
+    lp, ls, work = s.adjoint_buffers()
+    op, osc = s.adjoint_step(x, w[0].contiguous(), w[1].contiguous(), work)
+    rhs = float((v[0] * op).sum() + (v[1] * osc).sum())
+    assert abs(lhs - rhs) <= 1e-7 * abs(rhs), (lhs, rhs)
+    s.close()
+
+
+def _oracle_grad(p, P, u, T, nsteps):
+    u0 = torch.from_numpy(u).clone().requires_grad_(True)
+    T0 = torch.from_numpy(T).clone().requires_grad_(True)
+    st = OS.init_state(p, torch.from_numpy(P), u0, T0)
+    for _ in range(nsteps):
+        st, _ = OS.step(p, st)
+    _, rho, uu, scal, _ = OS.fields(p, st)
+    J = 0.5 * (rho * (uu * uu).sum(0)).sum() + ((scal[0] - scal[0].mean()) ** 2).sum()
+    J.backward()
+    return float(J.detach()), u0.grad.numpy(), T0.grad.numpy()
+
+
+def test_gradient_matches_oracle_autograd():
+    from paper_2207_11567_amd import Solver
+    from paper_2207_11567_amd.adjoint import rollout_objective
+    n, K = 10, 4
+    p = _params(n)
+    P, u, T = _fields(n)
+    Jo, gu_o, gT_o = _oracle_grad(p, P, u, T, K)
+    s = Solver(p)
+    u0 = torch.from_numpy(u).cuda().requires_grad_(True)
+    T0 = torch.from_numpy(T[0]).cuda().requires_grad_(True)
+    J = rollout_objective(s, u0, T0, torch.from_numpy(P).cuda(), K, seg=3)
+    J.backward()
+    assert abs(float(J) - Jo) <= 1e-12 * abs(Jo)
+    gu = u0.grad.cpu().numpy()
+    gT = T0.grad.cpu().numpy()[None]
+    assert np.linalg.norm(gu - gu_o) <= 1e-9 * np.linalg.norm(gu_o)
+    assert np.linalg.norm(gT - gT_o) <= 1e-9 * np.linalg.norm(gT_o)
+    s.close()
+
+
+def test_fp32_rollout_against_finite_differences():
+    from paper_2207_11567_amd import Solver
+    from paper_2207_11567_amd.adjoint import rollout_objective
+    n, K = 24, 60
+    p = _params(n, prec="fp32")
+    P, u, T = _fields(n, seed=5)
+    s = Solver(p)
+    Pd = torch.from_numpy(P).cuda()
+    u0 = torch.from_numpy(u).cuda().requires_grad_(True)
+    T0 = torch.from_numpy(T[0]).cuda().requires_grad_(True)
+    J = rollout_objective(s, u0, T0, Pd, K, seg=20)
+    J.backward()
+    gu, gT = u0.grad.detach(), T0.grad.detach()
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        du = torch.from_numpy(rng.standard_normal(u.shape)).cuda()
+        dT = torch.from_numpy(rng.standard_normal(T[0].shape)).cuda()
+        ad = float((gu * du).sum() + (gT * dT).sum())
+        eps = 1e-3 * float(u0.detach().abs().max())
+        with torch.no_grad():
+            Jp = float(rollout_objective(s, u0.detach() + eps * du, T0.detach() + eps * dT, Pd, K, 20))
+            Jm = float(rollout_objective(s, u0.detach() - eps * du, T0.detach() - eps * dT, Pd, K, 20))
+        fd = (Jp - Jm) / (2 * eps)
+        assert abs(fd - ad) <= 2e-2 * abs(fd), (fd, ad)
+    s.close()
+
+
+def test_adjoint_rejects_unsupported_configurations():
+    from paper_2207_11567_amd import Solver
+    from paper_2207_11567_amd._capi import LBM_E_UNSUPPORTED, LbmError
+    p = _params(8)
+    p["face_bc"] = ["wall"] * 6
+    s = Solver(p)
+    with pytest.raises(LbmError) as e:
+        s.adjoint_buffers()
+    assert e.value.status == LBM_E_UNSUPPORTED
+    s.close()
