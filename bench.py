@@ -199,6 +199,56 @@ def precision_errors(steps=200, n=64):
     return out
 
 
+def differentiation(nsteps=2000, seg=100, n=128):
+    """Cost of the hand-written adjoint on the differentiation workload: 128^3 D3Q27 FP32
+    with a passive temperature, J = sum rho|u|^2/2 + sum (T - mean T)^2 after nsteps,
+    checkpoints every seg steps."""
+    import torch
+
+    from paper_2207_11567_amd import Solver
+    from paper_2207_11567_amd.adjoint import rollout_objective
+    p, P, u = L.hit(n, seed=11567)
+    T = L.passive_field(n)
+    p.update(physics="passive", prandtl=0.7, weno_scale=[1.0] * 8, precision="fp32")
+    s = Solver(p, device="cuda:0")
+    Pd = torch.from_numpy(P).cuda()
+    u0 = torch.from_numpy(u).cuda().requires_grad_(True)
+    T0 = torch.from_numpy(T).cuda().requires_grad_(True)
+    rollout_objective(s, u0.detach(), T0.detach(), Pd, 50, 25)        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.time()
+    J = rollout_objective(s, u0, T0, Pd, nsteps, seg)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.time()
+    # per-step kernel costs on a fixed state
+    state = s.get_state()
+    lp, ls, work = s.adjoint_buffers()
+    lp.normal_()
+    ls.normal_()
+    out = (torch.empty_like(state[0]), torch.empty_like(state[1]))
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    reps = 50
+    e[0].record()
+    for _ in range(reps):
+        s.step_from(state[:2], out, 0)
+    e[1].record()
+    for _ in range(reps):
+        s.adjoint_step(state[:2], lp, ls, work)
+    e[2].record()
+    torch.cuda.synchronize()
+    fwd_ms = e[0].elapsed_time(e[1]) / reps
+    adj_ms = e[1].elapsed_time(e[2]) / reps
+    s.close()
+    return {"case": f"{n}^3 D3Q27 FP32 passive T, {nsteps} steps, checkpoints every {seg}",
+            "J": float(J.detach()), "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+            "backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
+            "step_ms": round(fwd_ms, 4), "adjoint_step_ms": round(adj_ms, 4),
+            "adjoint_step_over_step": round(adj_ms / fwd_ms, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +305,8 @@ def main():
                                        "cells": r["cells"], "desc": r["desc"]}
             print(f"# {name} {prec}: {r['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
         extra["precision_error_vs_fp64"] = precision_errors()
+        extra["differentiation"] = differentiation()
+        print(f"# differentiation: {extra['differentiation']}", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(args.workload)
     line = {
         "metric": "MLUPS of full hybrid step, % HBM roofline; FP16/32 vs FP64 error; adjoint/fwd",

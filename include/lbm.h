@@ -123,6 +123,12 @@ lbm_status lbm_step(lbm_solver *s, int32_t nsteps);
 lbm_status lbm_fields(lbm_solver *s, double *P_h, double *rho, double *u, double *scal,
                       double *sums_host);
 
+/* One time step from an explicit state (populations and scalars in the storage format,
+ * at level `step`) into explicit output buffers, leaving the solver's own state alone;
+ * used to refill a checkpoint segment before its adjoint steps.  Asynchronous. */
+lbm_status lbm_step_from(lbm_solver *s, const void *pops_in, const void *scal_in,
+                         void *pops_out, void *scal_out, int64_t step);
+
 /* The 8 sums formed by the last lbm_step (at the level of its last step).  Synchronises. */
 lbm_status lbm_step_sums(lbm_solver *s, double *sums_host);
 

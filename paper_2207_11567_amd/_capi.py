@@ -74,6 +74,7 @@ def _load():
         "lbm_step": [c_void_p, c_int32],
         "lbm_fields": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(c_double)],
         "lbm_step_sums": [c_void_p, P(c_double)],
+        "lbm_step_from": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_int64],
         "lbm_get_state": [c_void_p, c_void_p, c_void_p, P(ctypes.c_int64)],
         "lbm_set_state": [c_void_p, c_void_p, c_void_p, ctypes.c_int64],
         "lbm_adjoint_sizes": [c_void_p, P(c_size_t), P(c_size_t), P(c_size_t)],

@@ -38,12 +38,12 @@ class HybridRollout(torch.autograd.Function):
         op, osc = torch.empty_like(lp), torch.empty_like(ls)
         for c, (pops, scal, step) in reversed(list(enumerate(ctx.ckpts))):
             k = min(ctx.seg, ctx.nsteps - c * ctx.seg)
-            s.set_state(pops, scal if s.NS else None, step)
+            # recompute the segment's states straight into its buffer
             states = [(pops, scal)]
-            for _ in range(k - 1):
-                s.step(1)
-                p2, s2, _ = s.get_state()
-                states.append((p2, s2))
+            for j in range(k - 1):
+                nxt = (torch.empty_like(pops), torch.empty_like(scal))
+                s.step_from(states[-1], nxt, step + j)
+                states.append(nxt)
             for st in reversed(states):
                 s.adjoint_step(st, lp, ls, work, op, osc)
                 lp, op = op, lp

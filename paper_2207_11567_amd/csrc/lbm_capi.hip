@@ -298,6 +298,25 @@ lbm_status lbm_step(lbm_solver *s, int32_t nsteps) {
   return LBM_OK;
 }
 
+lbm_status lbm_step_from(lbm_solver *s, const void *pops_in, const void *scal_in, void *pops_out, void *scal_out,
+                         int64_t step) {
+  if (!s) return LBM_E_INVALID;
+  if (!pops_in || !pops_out || pops_in == pops_out || step < 0 ||
+      (s->NS > 0 && (!scal_in || !scal_out || scal_in == scal_out))) {
+    s->err = "lbm_step_from: distinct input and output buffers are required";
+    return LBM_E_INVALID;
+  }
+  StepArgs a = make_args(s);
+  a.pop_in = pops_in;
+  a.pop_out = pops_out;
+  a.scal_in = scal_in;
+  a.scal_out = scal_out;
+  a.step = step;
+  hipError_t e = launch(s, LAUNCH_STEP, a);
+  if (e != hipSuccess) return hip_fail(s, e, "step kernel");
+  return LBM_OK;
+}
+
 lbm_status lbm_step_sums(lbm_solver *s, double *sums_host) {
   if (!s) return LBM_E_INVALID;
   hipError_t e = launch_finalize(s->partials, s->nblocks, s->stage, s->sums, s->stream);

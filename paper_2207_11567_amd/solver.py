@@ -98,6 +98,11 @@ class Solver:
                                      _ptr(S) if self.NS else None, sums))
         return {"P_h": P, "rho": rho, "u": u, "scal": S[:self.NS], "sums": list(sums)}
 
+    def step_from(self, state, out, step):
+        """One step from state = (pops, scal) into out = (pops, scal)."""
+        self._chk(C.lib().lbm_step_from(self._h, _ptr(state[0]), _ptr(state[1]) if self.NS else None,
+                                        _ptr(out[0]), _ptr(out[1]) if self.NS else None, int(step)))
+
     def step_sums(self):
         sums = (ctypes.c_double * 8)()
         self._chk(C.lib().lbm_step_sums(self._h, sums))

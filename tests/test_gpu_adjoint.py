@@ -134,3 +134,72 @@ def test_adjoint_rejects_unsupported_configurations():
         s.adjoint_buffers()
     assert e.value.status == LBM_E_UNSUPPORTED
     s.close()
+
+
+def test_gradient_matches_oracle_on_32_cube():
+    """The 32^3 FP64 copy of the differentiation workload (3 steps) against autograd
+    through the oracle, checkpointed per step to bound host memory."""
+    from torch.utils.checkpoint import checkpoint
+
+    from paper_2207_11567_amd import Solver
+    from paper_2207_11567_amd.adjoint import rollout_objective
+    n, K = 32, 3
+    p = _params(n)
+    P, u, T = _fields(n, seed=11)
+    u0 = torch.from_numpy(u).clone().requires_grad_(True)
+    T0 = torch.from_numpy(T).clone().requires_grad_(True)
+    st = OS.init_state(p, torch.from_numpy(P), u0, T0)
+    pops, scal = st["pops"], st["scal"]
+
+    def one(pp, ss, k):
+        nxt, _ = OS.step(p, {"pops": pp, "scal": ss, "step": k, "solid": st["solid"]})
+        return nxt["pops"], nxt["scal"]
+
+    for k in range(K):
+        pops, scal = checkpoint(one, pops, scal, k, use_reentrant=False)
+    _, rho, uu, sc, _ = OS.fields(p, {"pops": pops, "scal": scal, "step": K, "solid": st["solid"]})
+    J = 0.5 * (rho * (uu * uu).sum(0)).sum() + ((sc[0] - sc[0].mean()) ** 2).sum()
+    J.backward()
+    s = Solver(p)
+    ug = torch.from_numpy(u).cuda().requires_grad_(True)
+    Tg = torch.from_numpy(T[0]).cuda().requires_grad_(True)
+    Jg = rollout_objective(s, ug, Tg, torch.from_numpy(P).cuda(), K, seg=2)
+    Jg.backward()
+    assert abs(float(Jg) - float(J.detach())) <= 1e-12 * abs(float(J.detach()))
+    e_u = np.linalg.norm(ug.grad.cpu().numpy() - u0.grad.numpy()) / np.linalg.norm(u0.grad.numpy())
+    e_T = np.linalg.norm(Tg.grad.cpu().numpy() - T0.grad.numpy()[0]) / np.linalg.norm(T0.grad.numpy())
+    print(f"32^3 gradient relative L2 error: u {e_u:.3e}, T {e_T:.3e}")
+    assert e_u <= 1e-9 and e_T <= 1e-9
+    s.close()
+
+
+def test_full_size_fp32_rollout_finite_differences():
+    """128^3 FP32, 2000 steps, checkpoints every 100: gradient against central differences
+    of J (FP64 sums) along random directions."""
+    from paper_2207_11567_amd import Solver
+    from paper_2207_11567_amd.adjoint import rollout_objective
+    n, K = 128, 2000
+    p = _params(n, prec="fp32")
+    P, u, T = _fields(n, seed=7)
+    s = Solver(p)
+    Pd = torch.from_numpy(P).cuda()
+    u0 = torch.from_numpy(u).cuda().requires_grad_(True)
+    T0 = torch.from_numpy(T[0]).cuda().requires_grad_(True)
+    J = rollout_objective(s, u0, T0, Pd, K, seg=100)
+    J.backward()
+    gu, gT = u0.grad.detach(), T0.grad.detach()
+    rng = np.random.default_rng(3)
+    errs = []
+    for _ in range(4):
+        du = torch.from_numpy(rng.standard_normal(u.shape)).cuda()
+        dT = torch.from_numpy(rng.standard_normal(T[0].shape)).cuda()
+        ad = float((gu * du).sum() + (gT * dT).sum())
+        eps = 1e-3 * float(u0.detach().abs().max())
+        with torch.no_grad():
+            Jp = float(rollout_objective(s, u0.detach() + eps * du, T0.detach() + eps * dT, Pd, K, 100))
+            Jm = float(rollout_objective(s, u0.detach() - eps * du, T0.detach() - eps * dT, Pd, K, 100))
+        fd = (Jp - Jm) / (2 * eps)
+        errs.append(abs(fd - ad) / abs(fd))
+    print("128^3 x 2000 FD relative errors:", ["%.2e" % e for e in errs])
+    assert max(errs) <= 2e-2, errs
+    s.close()
