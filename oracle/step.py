@@ -44,9 +44,11 @@ def inlet_velocity(params, grid, n):
     scale = torch.ones(grid.shape, dtype=torch.float64)
     if face_axis is not None and amp != 0.0:
         others = [a for a in range(3) if a != face_axis]
-        coords = grid.coord + [torch.zeros_like(grid.coord[0])] * (3 - len(grid.coord))
+        # coordinates in the full domain (a sub-window declares its origin)
+        origin = params.get("noise_origin", (0, 0, 0))
+        coords = [grid.coord[d] + int(origin[d]) for d in range(3)]
         a_c = coords[others[0]].numpy()
-        b_c = coords[others[1]].numpy() if len(others) > 1 else 0 * a_c
+        b_c = coords[others[1]].numpy()
         xi = noise.xi(params["seed"], a_c, b_c, n)
         scale = 1.0 + amp * torch.from_numpy(xi)
     return u_in.reshape(D, 1, 1, 1) * scale

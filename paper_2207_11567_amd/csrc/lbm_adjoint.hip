@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(KArgs<typename Prec<PREC>:
 #pragma unroll
   for (int i = 0; i < 27; ++i) lam[i] = lamB[i * N + n];
   Rates<R> rt;
-  rt.tau0 = viscosity(a.th, rho0) / s + R(0.5);
+  rt.tau0 = viscosity(a.th, rho0) * R(3) + R(0.5);
   rt.smag18 = a.smag18;
   rt.wb = a.wb;
   rt.wh = a.wh;

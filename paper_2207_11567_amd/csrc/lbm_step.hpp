@@ -548,7 +548,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
         for (int i = 0; i < Q; ++i) e[i] -= R(wgt<Q>(i)) * Es;   // d = f~ - w
         const R nu = viscosity(a.th, rho0);
         Rates<R> rt;
-        rt.tau0 = nu / s + R(0.5);
+        rt.tau0 = nu * R(3) + R(0.5);                    // nu / cs2 + 1/2
         rt.smag18 = a.smag18;
         rt.wb = a.wb;
         rt.wh = a.wh;
