@@ -261,9 +261,14 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
                     help="time the main workload only (for profiler runs)")
+    ap.add_argument("--diff-only", action="store_true",
+                    help="run a 200-step differentiation of the 128^3 workload (for profiler runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain 1 GiB device copy 3 times (counter calibration) and exit")
     args = ap.parse_args()
+    if args.diff_only:
+        print(json.dumps(differentiation(nsteps=200, seg=100)))
+        return
     if args.copy_calib:
         import torch
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
