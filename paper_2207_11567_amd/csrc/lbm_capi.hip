@@ -143,6 +143,13 @@ static StepArgs make_args(const lbm_solver *s) {
   a.step = s->step;
   a.collision = p.collision;
   a.remap = 1;
+  a.band_rows = 0;
+  if (p.nx % 64 == 0 && p.ny % 4 == 0)
+    for (int b : {32, 16, 8, 4})
+      if (p.ny % b == 0) {
+        a.band_rows = b;
+        break;
+      }
   a.P0 = p.rho_ref / 3.0;
   a.wb = p.omega_bulk;
   a.wh = p.omega_high;

@@ -38,6 +38,7 @@ struct StepArgs {
   long long step;
   int collision;       // 0 cumulant, 1 BGK
   int remap;           // XCD-aware block order
+  int band_rows;       // 0: linear 256-cell tiles; else 64x4 tiles in bands of this many rows
   double P0;           // rho_ref cs2
   double wb, wh, smag18;
   double inlet_u[3], inlet_noise, outlet_P;
@@ -61,7 +62,7 @@ template <class R> struct KArgs {
   int nx, ny, nz, N;
   int face[6];
   long long step;
-  int collision, remap;
+  int collision, remap, band_rows;
   R P0, invP0, wb, wh, smag18;
   R inlet_u[3], outlet_P;
   double inlet_noise;
@@ -78,7 +79,7 @@ template <class R> KArgs<R> to_kargs(const StepArgs &a) {
   k.f_P = a.f_P; k.f_rho = a.f_rho; k.f_u = a.f_u; k.f_scal = a.f_scal;
   k.nx = a.nx; k.ny = a.ny; k.nz = a.nz; k.N = (int)a.N;
   for (int f = 0; f < 6; ++f) k.face[f] = a.face[f];
-  k.step = a.step; k.collision = a.collision; k.remap = a.remap;
+  k.step = a.step; k.collision = a.collision; k.remap = a.remap; k.band_rows = a.band_rows;
   k.P0 = (R)a.P0; k.invP0 = (R)(1.0 / a.P0); k.wb = (R)a.wb; k.wh = (R)a.wh; k.smag18 = (R)a.smag18;
   for (int d = 0; d < 3; ++d) k.inlet_u[d] = (R)a.inlet_u[d];
   k.outlet_P = (R)a.outlet_P; k.inlet_noise = a.inlet_noise;
@@ -164,6 +165,14 @@ template <class T> __device__ __forceinline__ T ldg(const T *base, unsigned idx)
 template <class T> __device__ __forceinline__ void stg(T *base, unsigned idx, T v) {
   *(T *)((char *)base + idx * (unsigned)sizeof(T)) = v;
 }
+// Streaming (non-temporal) variants for the populations, which are read once and written
+// once per step: they should not displace the reused scalar rows and planes from L2.
+template <class T> __device__ __forceinline__ T ldg_nt(const T *base, unsigned idx) {
+  return __builtin_nontemporal_load((const T *)((const char *)base + idx * (unsigned)sizeof(T)));
+}
+template <class T> __device__ __forceinline__ void stg_nt(T *base, unsigned idx, T v) {
+  __builtin_nontemporal_store(v, (T *)((char *)base + idx * (unsigned)sizeof(T)));
+}
 
 
 // Block reduction of 8 doubles into partials[tile*8 ..] in a fixed order: every thread
@@ -200,7 +209,22 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
   constexpr R s = R(1.0 / 3.0);
 
   const int tile = tile_of_block(blockIdx.x, gridDim.x, a.remap);
-  const int n = tile * (int)blockDim.x + (int)threadIdx.x;
+  // Banded tile order: 64x4-cell tiles, visited band of rows by band, and inside a band
+  // plane by plane, so the +-1 and +-2 planes of the scalar stencils were touched a few
+  // dozen tiles earlier and are still in L2.
+  int n;
+  if (a.band_rows) {
+    const int nxt = a.nx >> 6, bt = a.band_rows >> 2;
+    const int per_plane = nxt * bt, per_band = per_plane * a.nz;
+    const int band = tile / per_band, r = tile - band * per_band;
+    const int zz = r / per_plane, r2 = r - zz * per_plane;
+    const int xt = r2 / bt, ys = r2 - xt * bt;
+    const int xx = (xt << 6) + ((int)threadIdx.x & 63);
+    const int yy = band * a.band_rows + (ys << 2) + ((int)threadIdx.x >> 6);
+    n = xx + a.nx * (yy + a.ny * zz);
+  } else {
+    n = tile * (int)blockDim.x + (int)threadIdx.x;
+  }
   double red[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int N = a.N;
   const unsigned un = (unsigned)n;
@@ -282,7 +306,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const unsigned m = un + (unsigned)(off[0][2 - cx(i)] + off[1][2 - cy(i)] + (D == 3 ? off[2][2 - cz(i)] : 0));
-          gh[i] = decode<R>(ldg(pin + (size_t)i * N, m));
+          gh[i] = decode<R>(ldg_nt(pin + (size_t)i * N, m));
         }
       } else {
         // boundary cell: bounce-back, moving-wall inlet, anti-bounce-back outlet
@@ -343,7 +367,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
                     R(2.0 * wgt<Q>(i)) * ((R(a.outlet_P) + rho0 * (cu * cu * R(1.5) - uo2 * R(0.5))) * invP0 - R(1));
           } else {
             const unsigned m = un + (unsigned)(off[0][2 - c[0]] + off[1][2 - c[1]] + (D == 3 ? off[2][2 - c[2]] : 0));
-            gh[i] = decode<R>(ldg(pin + (size_t)i * N, m));
+            gh[i] = decode<R>(ldg_nt(pin + (size_t)i * N, m));
           }
         }
       }
@@ -564,7 +588,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             R gs;
             if constexpr (NS >= 2) gs = R(wgt<Q>(i)) * base + e[i] * invr + Xi[i] * hP0;   // Eq. 8
             else gs = R(wgt<Q>(i)) * base + e[i];
-            stg(pout + (size_t)i * N, un, encode<St>(gs));
+            stg_nt(pout + (size_t)i * N, un, encode<St>(gs));
           }
         } else {
           // BGK in the pre-conditioned frame (Eq. 5 with the half-source split)
@@ -578,7 +602,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             R xh = R(0);
             if constexpr (NS >= 2) xh = Xi[i] * hP0;
             const R gp = gh[i] + xh;
-            stg(pout + (size_t)i * N, un, encode<St>(gp - om * (gp - geq) + xh));
+            stg_nt(pout + (size_t)i * N, un, encode<St>(gp - om * (gp - geq) + xh));
           }
         }
         bad |= !isfinite(Ph + u[0] + u[1] + u[2]);
