@@ -18,7 +18,8 @@ Readings (the paper defers the coupling details to earlier work):
   scalar's range, upwinded per axis on the sign of u_d at the cell (u_d >= 0 left-biased).
 * Ghost values for stencils at walls/solids are mirror images about the wall face; at the
   inlet the inlet value; at the outlet the nearest interior value.
-* Ideal gas at constant thermodynamic pressure: rho = rho_ref (T_ref/T)(W/W_ref).
+* Ideal gas: rho = rho_ref (T_ref/T)(W/W_ref) pi, pi = P_th/P_th(0) the thermodynamic
+  pressure relative to the one at which rho_ref is given (pi = 1 in an open domain).
 """
 import torch
 
@@ -37,15 +38,26 @@ def mixture_W(params, Y):
     return 1.0 / inv
 
 
-def density(params, scal, shape):
+def density(params, scal, shape, pth=1.0):
     phys = params["physics"]
     if phys in ("isothermal", "passive"):
         return torch.full(shape, float(params["rho_ref"]), dtype=torch.float64)
     T = scal[0]
     if phys == "one_step":
-        return params["rho_ref"] * params["T_ref"] / T
+        return params["rho_ref"] * params["T_ref"] / T * pth
     W = mixture_W(params, scal[1:])
-    return params["rho_ref"] * (params["T_ref"] / T) * (W / params["chem"][17])
+    return params["rho_ref"] * (params["T_ref"] / T) * (W / params["chem"][17]) * pth
+
+
+def w_over_T(params, scal, shape):
+    """W/T per cell: the density per unit thermodynamic pressure up to a constant
+    (1/T for the one-step model's constant W, 1/T_ref without a temperature)."""
+    phys = params["physics"]
+    if phys in ("isothermal", "passive"):
+        return torch.full(shape, 1.0 / float(params["T_ref"]), dtype=torch.float64)
+    if phys == "one_step":
+        return 1.0 / scal[0]
+    return mixture_W(params, scal[1:]) / scal[0]
 
 
 def viscosity(params, rho):

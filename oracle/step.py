@@ -8,7 +8,9 @@ scalars (T, Y_1..) at level n, and the step counter n.  One step, for every cell
  3. P_h, u from Eq. 7;  4. grad(rho) by central differences;  5. Xi (Eq. 2);
  6. f' (Eq. 13);  7. collision (cumulant, Eq. 9 as read; or BGK in the same frame);
  8. g* (Eq. 8);  9. explicit Euler update of the scalars with u^n (Sec. 2.3);
-10. FP64 sums over fluid cells at level n.
+10. FP64 sums over fluid cells at level n;
+11. closed domains only: the thermodynamic pressure of level n+1 from mass conservation
+    (module pressure), whose rate also enters steps 2 and 9.
 Solid cells keep their populations and scalars unchanged.
 
 Boundary readings (the paper names no-slip/zero-flux/adiabatic walls, an inlet and an
@@ -23,7 +25,7 @@ first of wall, inlet, outlet.  Periodic faces wrap.
 """
 import torch
 
-from . import cumulant, equations, noise, scalars
+from . import cumulant, equations, noise, pressure, scalars
 from .grid import INLET, OUTLET, SOLID, Grid
 from .lattice import CS2, get as get_lattice
 
@@ -104,7 +106,12 @@ def init_state(params, P_h, u, scal, solid=None):
                                                                        dtype=torch.float64)
     rho = scalars.density(params, scal, grid.shape)
     A = equations.g_eq(lat, P_h.to(torch.float64), rho, u.to(torch.float64))
-    return {"pops": A, "scal": scal.clone(), "step": 0, "solid": grid.solid}
+    return {"pops": A, "scal": scal.clone(), "step": 0, "solid": grid.solid,
+            "thermo": pressure.initial()}
+
+
+def _thermo(state):
+    return state.get("thermo", pressure.initial())
 
 
 def _level_n(params, state):
@@ -112,9 +119,11 @@ def _level_n(params, state):
     lat = get_lattice(params["lattice"])
     grid = _grid_of(params, state["solid"])
     scal = state["scal"]
-    rho = scalars.density(params, scal, grid.shape)
+    thermo = _thermo(state)
+    rho = scalars.density(params, scal, grid.shape, thermo[0])
     g = pull(params, lat, grid, state["pops"], rho, state["step"])
     R, Lam = scalars.nonadvective_rhs(params, grid, scal, rho)
+    R, Lam = pressure.apply(params, R, Lam, scal[0] if scal.shape[0] else None, thermo)
     P_h, u = equations.moments(lat, g, rho, Lam)
     if params["physics"] in ("one_step", "two_step"):
         rho_in = scalars.density(params, scalars.inlet_scalars(params).reshape(-1, 1, 1, 1),
@@ -125,6 +134,13 @@ def _level_n(params, state):
     return lat, grid, rho, g, R, Lam, P_h, u, grad_rho
 
 
+def _w_over_T_sum(params, grid, scal):
+    f = grid.fluid
+    if params["physics"] in ("isothermal", "passive"):
+        return float(f.sum()) / float(params["T_ref"])
+    return float(scalars.w_over_T(params, scal, grid.shape)[f].sum())
+
+
 def reductions(params, grid, rho, P_h, u, scal):
     f = grid.fluid
     out = torch.zeros(8, dtype=torch.float64)
@@ -133,13 +149,7 @@ def reductions(params, grid, rho, P_h, u, scal):
     for d in range(grid.D):
         out[2 + d] = (rho * u[d])[f].sum()
     out[5] = 0.5 * (rho * (u * u).sum(0))[f].sum()
-    phys = params["physics"]
-    if phys in ("isothermal", "passive"):
-        out[6] = float(f.sum()) / float(params["T_ref"])
-    elif phys == "one_step":
-        out[6] = (1.0 / scal[0])[f].sum()
-    else:
-        out[6] = (scalars.mixture_W(params, scal[1:]) / scal[0])[f].sum()
+    out[6] = _w_over_T_sum(params, grid, scal)
     if scal.shape[0] >= 2:
         out[7] = (rho * scal[1])[f].sum()
     return out
@@ -167,8 +177,11 @@ def step(params, state):
     if new_scal.shape[0]:
         new_scal = torch.where(solid, state["scal"], new_scal)
     sums = reductions(params, grid, rho, P_h, u, state["scal"])
+    thermo = _thermo(state)
+    if pressure.closed(params):
+        thermo = pressure.update(thermo, float(sums[6]), _w_over_T_sum(params, grid, new_scal))
     return ({"pops": gs, "scal": new_scal, "step": state["step"] + 1,
-             "solid": state["solid"]}, sums)
+             "solid": state["solid"], "thermo": thermo}, sums)
 
 
 def fields(params, state):
