@@ -14,6 +14,16 @@
  * a velocity inlet and a pressure outlet.  Global FP64 sums (mass, pressure, momentum,
  * kinetic energy, thermodynamic-pressure integral) are formed every step.
  *
+ * Closed domains (pth_mode = LBM_PTH_CLOSED; the confined deflagration of Sec. 3.1, whose
+ * pressure climbs as the flame accelerates): Eq. 3 holds at a constant thermodynamic
+ * pressure P_th and the paper gives no closed-domain form, so the library takes the usual
+ * low-Mach one.  pi = P_th/P_th(0) scales the ideal-gas density; q = dln(pi)/dt adds the
+ * pressure work kappa T q (kappa = (gamma-1)/gamma) to the temperature right-hand side and
+ * the velocity divergence that enters Xi (Eq. 2) and P_h (Eq. 7a) is Lambda - q; after
+ * each step pi is set so that the total mass sum rho over fluid cells is that of level 0
+ * (pi' = K / sum W/T of the updated scalars, K = pi sum W/T at level 0) and q is the
+ * backward difference (pi' - pi)/pi, used by the next step.
+ *
  * Conventions
  *  - Lattice units: dr = dt = 1, cs^2 = 1/3.  P0 = rho_ref cs^2.
  *  - Cells are ordered x fastest: n = x + nx (y + ny z); nz = 1 for D2Q9.
@@ -63,6 +73,7 @@ enum { LBM_CUMULANT = 0, LBM_BGK = 1 };
 enum { LBM_ISOTHERMAL = 0, LBM_PASSIVE = 1, LBM_ONE_STEP = 2, LBM_TWO_STEP = 3 };
 enum { LBM_VISC_CONST_NU = 0, LBM_VISC_CONST_MU = 1 };
 enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_INLET = 2, LBM_OUTLET = 3 };
+enum { LBM_PTH_OPEN = 0, LBM_PTH_CLOSED = 1 };
 
 /* Problem statement (Sec. 2 and 3 of the paper), lattice units. */
 typedef struct {
@@ -89,6 +100,8 @@ typedef struct {
   double chem[32];    /* LBM_ONE_STEP: B, Ta, T_u, T_ad, Y_u.
                          LBM_TWO_STEP: B1, Ta1, B2, Ta2, c_p, W_k[6], h_k[6], W_ref. */
   uint64_t seed;      /* counter-based inlet noise (SplitMix64) */
+  int32_t pth_mode;   /* LBM_PTH_OPEN (constant P_th, Eq. 3) | LBM_PTH_CLOSED (mass held) */
+  double gamma;       /* ratio of specific heats (closed domains; must exceed 1) */
 } lbm_params;
 
 /* Sizes (bytes) of the caller-provided device buffers for these parameters: one
@@ -99,7 +112,8 @@ lbm_status lbm_query_sizes(const lbm_params *p, size_t *pop_bytes, size_t *scal_
                            size_t *work_bytes);
 
 /* Validates parameters (tau0 > 1/2, F D max <= 1/(2 d) Fourier limit at rho_ref,
- * nz == 1 for D2Q9, sizes > 0, 0 <= omegas <= 2) and binds the buffers.  stream is a
+ * nz == 1 for D2Q9, sizes > 0, 0 <= omegas <= 2; a closed domain has no inlet or outlet
+ * face and gamma > 1) and binds the buffers.  stream is a
  * hipStream_t (NULL = default stream).  scal_a/scal_b may be NULL when S == 0. */
 lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_b,
                       void *scal_a, void *scal_b, void *work, lbm_solver **out);
@@ -109,12 +123,13 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
 lbm_status lbm_set_geometry(lbm_solver *s, const uint8_t *solid_dev);
 
 /* Equilibrium initialisation (Eq. 6): post-collision populations of level -1 are set to
- * g_eq(P_h, rho(T, Y), u); scalars copied; step counter 0.  Device FP64 inputs; scal
- * may be NULL when S == 0. */
+ * g_eq(P_h, rho(T, Y), u); scalars copied; step counter 0; thermodynamic pressure
+ * (pi, q, K) = (1, 0, 0).  Device FP64 inputs; scal may be NULL when S == 0. */
 lbm_status lbm_init_fields(lbm_solver *s, const double *P_h, const double *u,
                            const double *scal);
 
-/* Advances nsteps time steps (Eq. 1 + Sec. 2.3) asynchronously on the stream. */
+/* Advances nsteps time steps (Eq. 1 + Sec. 2.3) asynchronously on the stream.  A closed
+ * domain adds two small reduction launches per step (the pressure update). */
 lbm_status lbm_step(lbm_solver *s, int32_t nsteps);
 
 /* Fields at the current level n (P_h of Eq. 7a, rho, u of Eq. 7b, scalars), each pointer
@@ -125,7 +140,8 @@ lbm_status lbm_fields(lbm_solver *s, double *P_h, double *rho, double *u, double
 
 /* One time step from an explicit state (populations and scalars in the storage format,
  * at level `step`) into explicit output buffers, leaving the solver's own state alone;
- * used to refill a checkpoint segment before its adjoint steps.  Asynchronous. */
+ * used to refill a checkpoint segment before its adjoint steps.  Asynchronous.
+ * LBM_E_UNSUPPORTED in a closed domain (its pressure is solver state). */
 lbm_status lbm_step_from(lbm_solver *s, const void *pops_in, const void *scal_in,
                          void *pops_out, void *scal_out, int64_t step);
 
@@ -133,17 +149,25 @@ lbm_status lbm_step_from(lbm_solver *s, const void *pops_in, const void *scal_in
 lbm_status lbm_step_sums(lbm_solver *s, double *sums_host);
 
 /* Raw state copies (device-to-device, storage format): pops [Q][N], scal [S][N].
- * Synchronise. */
+ * Synchronise.  The thermodynamic pressure is copied separately (below). */
 lbm_status lbm_get_state(lbm_solver *s, void *pops_dst, void *scal_dst, int64_t *step);
 lbm_status lbm_set_state(lbm_solver *s, const void *pops_src, const void *scal_src,
                          int64_t step);
+
+/* Thermodynamic pressure state of the current level, three FP64 values on the host:
+ * pi = P_th/P_th(0), q = dln(pi)/dt of this level (per time step), K = the held
+ * mass constant (0 until the first step of a closed domain fixes it).  Open domains keep
+ * (1, 0, 0).  get synchronises; set (pi > 0, finite q, K >= 0, else LBM_E_INVALID) is
+ * queued on the stream, for restarts together with lbm_set_state. */
+lbm_status lbm_get_thermo_pressure(lbm_solver *s, double *pqk_host);
+lbm_status lbm_set_thermo_pressure(lbm_solver *s, const double *pqk_host);
 
 /* ------------------------------------------------------------------ differentiation
  * Discrete adjoint of one time step (reverse-mode vector-Jacobian product of the exact
  * discrete step: collision, Smagorinsky shear rate, WENO3 advection with its nonlinear
  * weights, centred diffusion, streaming).  Scope: D3Q27, periodic faces, no solid cells,
- * LBM_ISOTHERMAL or LBM_PASSIVE, LBM_CUMULANT with omega_high == 1, LBM_FP64 or LBM_FP32;
- * anything else returns LBM_E_UNSUPPORTED.  Adjoint arrays are in the compute precision
+ * LBM_ISOTHERMAL or LBM_PASSIVE, LBM_CUMULANT with omega_high == 1, LBM_FP64 or LBM_FP32,
+ * LBM_PTH_OPEN; anything else returns LBM_E_UNSUPPORTED.  Adjoint arrays are in the compute precision
  * (FP64 or FP32), laid out like the state: populations [27][N], scalars [S][N].
  * At the upwind switch u_d = 0 the derivative of |u_d| is taken as +1. */
 

@@ -159,6 +159,54 @@ def flame2d(nx=1024, ny=256, radius=20.0, width=2.0, Tu=300.0, Tb=2000.0, F=4.0,
     return params, P, u, scal, mask
 
 
+def chamber_mask(nx=2500, ny=500):
+    """Solid mask of the deflagration chamber of Sec. 3.1 (250 mm x 50 mm) on an nx x ny
+    grid (nx/250 cells per mm): three rows of five 3 mm x 4 mm baffles whose row centres
+    sit 20, 50 and 80 mm from the left wall, 9 mm apart vertically (centre to centre,
+    centred on the mid-height), and a 12 mm square obstacle whose upstream face is 94 mm
+    from the left wall, centred vertically."""
+    s = nx / 250.0
+    mask = np.zeros((1, ny, nx), dtype=bool)
+
+    def block(x0, x1, y0, y1):
+        mask[0, int(round(y0 * s)):int(round(y1 * s)), int(round(x0 * s)):int(round(x1 * s))] = True
+
+    for xc in (20.0, 50.0, 80.0):
+        for k in range(-2, 3):
+            yc = 25.0 + 9.0 * k
+            block(xc - 1.5, xc + 1.5, yc - 2.0, yc + 2.0)
+    block(94.0, 106.0, 19.0, 31.0)
+    return mask
+
+
+def chamber2d(nx=2500, ny=500, Tu=300.0, Tb=2000.0, F=4.0, FD=0.03, cs_smag=0.17, closed=True,
+              gamma=1.4, precision="fp64"):
+    """Closed 2-D deflagration chamber of Sec. 3.1 on the paper's 2500 x 500 grid
+    (0.1 mm cells): walls on all four sides, the obstacles of chamber_mask, burnt gas in a
+    half-disc of radius 10 mm at the middle of the left wall (tanh edge of 2 cells), the
+    one-step chemistry and thickened-flame settings of flame2d, and (closed=True) the
+    thermodynamic pressure held by the mass the chamber contains."""
+    mask = chamber_mask(nx, ny)
+    radius = 10.0 * nx / 250.0
+    x = np.arange(nx)[None, None, :] + 0.5
+    y = np.arange(ny)[None, :, None] + 0.5
+    r = np.sqrt(x ** 2 + (y - ny / 2.0) ** 2)
+    theta = 0.5 * (1.0 - np.tanh((r - radius) / 2.0))
+    T = Tu + (Tb - Tu) * theta
+    Y = 1.0 - theta
+    scal = np.stack([T, Y]).reshape(2, 1, ny, nx)
+    P = np.full((1, ny, nx), CS2)
+    u = np.zeros((2, 1, ny, nx))
+    D_u = FD / F
+    params = base_params("D2Q9", nx, ny, 1, physics="one_step", visc_law="const_mu",
+                         nu_ref=0.7 * D_u, prandtl=0.7, thickening=F, cs_smag=cs_smag,
+                         T_ref=Tu, face_bc=["wall", "wall", "wall", "wall", "periodic", "periodic"],
+                         inlet_T=Tu, weno_scale=[Tb - Tu, 1.0],
+                         chem=list(ONE_STEP_CHEM[:2]) + [Tu, Tb, 1.0],
+                         pth_mode="closed" if closed else "open", gamma=gamma, precision=precision)
+    return params, P, u, scal, mask
+
+
 def reacting_box(nx=192, ny=192, nz=384, u_in=0.1, noise=0.05, phi=0.83, T_in=320.0,
                  T_b=1950.0, F=5.0, nu=5e-4, cs_smag=0.17, seed=2207, chem=None):
     """3-D box, periodic in x and y, inlet at z = 0 and outlet at z = nz-1, fresh CH4/air

@@ -18,6 +18,7 @@ COLLISION = {"cumulant": 0, "bgk": 1}
 PHYSICS = {"isothermal": 0, "passive": 1, "one_step": 2, "two_step": 3}
 VISC = {"const_nu": 0, "const_mu": 1}
 FACE = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
+PTH = {"open": 0, "closed": 1}
 N_SCALARS = {"isothermal": 0, "passive": 1, "one_step": 2, "two_step": 6}
 
 
@@ -30,7 +31,8 @@ class LbmParams(ctypes.Structure):
                 ("rho_ref", c_double), ("T_ref", c_double),
                 ("face_bc", c_int32 * 6), ("inlet_u", c_double * 3), ("inlet_noise", c_double),
                 ("outlet_P", c_double), ("inlet_T", c_double), ("inlet_Y", c_double * 8),
-                ("weno_scale", c_double * 8), ("chem", c_double * 32), ("seed", c_uint64)]
+                ("weno_scale", c_double * 8), ("chem", c_double * 32), ("seed", c_uint64),
+                ("pth_mode", c_int32), ("gamma", c_double)]
 
 
 def make_params(d):
@@ -56,6 +58,8 @@ def make_params(d):
     for i, v in enumerate(list(d["chem"])[:32]):
         p.chem[i] = float(v)
     p.seed = int(d["seed"]) & 0xFFFFFFFFFFFFFFFF
+    p.pth_mode = PTH[d.get("pth_mode", "open")]
+    p.gamma = float(d.get("gamma", 1.4))
     return p
 
 
@@ -82,6 +86,8 @@ def _load():
                              c_void_p],
         "lbm_objective": [c_void_p, c_void_p, c_void_p, P(c_double), c_void_p, c_void_p],
         "lbm_init_adjoint": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+        "lbm_get_thermo_pressure": [c_void_p, P(c_double)],
+        "lbm_set_thermo_pressure": [c_void_p, P(c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

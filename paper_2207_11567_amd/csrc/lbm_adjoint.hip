@@ -151,7 +151,9 @@ __global__ __launch_bounds__(256) void objective_kernel(KArgs<typename Prec<PREC
   constexpr R s = R(1.0 / 3.0);
   const int n = blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
   const int N = a.N;
-  double red[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double red[NSUM];
+#pragma unroll
+  for (int k = 0; k < NSUM; ++k) red[k] = 0.0;
   if (n < N) {
     const unsigned un = (unsigned)n;
     const St *__restrict__ pin = (const St *)a.pop_in;
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(256) void objective_kernel(KArgs<typename Prec<PREC
       if (NS) lamT[n] = R(2) * (T - R(mean_T));
     }
   }
-  if (pass == 0) block_sums(red, a.partials + (size_t)blockIdx.x * 8);
+  if (pass == 0) block_sums(red, a.partials + (size_t)blockIdx.x * NSUM);
 }
 
 // Reverse of the equilibrium initialisation (Eq. 6) with respect to u0 (FP64 fields).

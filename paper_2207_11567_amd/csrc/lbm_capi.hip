@@ -27,6 +27,8 @@ struct lbm_solver {
   double *sums;
   double *partials;
   double *stage;
+  double *thermo;     // (pi, q, K) of the closed-domain thermodynamic pressure
+  bool closed;
   void *geom;
   std::string err;
 };
@@ -50,7 +52,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   long long N;
   int Q, NS, D, nblocks;
-  size_t pop_bytes, scal_bytes, off_flag, off_sums, off_stage, off_partials, off_geom, work_bytes;
+  size_t pop_bytes, scal_bytes, off_flag, off_sums, off_thermo, off_stage, off_partials, off_geom, work_bytes;
 };
 
 static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
@@ -92,6 +94,13 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   const int Dm = p->lattice == LBM_D2Q9 ? 2 : 3;
   for (int f = 0; f < 6; ++f)
     if (p->face_bc[f] < LBM_PERIODIC || p->face_bc[f] > LBM_OUTLET) return fail("unknown face condition");
+  if (p->pth_mode != LBM_PTH_OPEN && p->pth_mode != LBM_PTH_CLOSED) return fail("unknown pth_mode");
+  if (p->pth_mode == LBM_PTH_CLOSED) {
+    if (!(p->gamma > 1.0) || !isfinite(p->gamma)) return fail("closed domain needs gamma > 1");
+    for (int f = 0; f < 2 * Dm; ++f)
+      if (p->face_bc[f] == LBM_INLET || p->face_bc[f] == LBM_OUTLET)
+        return fail("a closed domain has no inlet or outlet face");
+  }
   for (int d = 0; d < Dm; ++d)
     if ((p->face_bc[2 * d] == LBM_PERIODIC) != (p->face_bc[2 * d + 1] == LBM_PERIODIC))
       return fail("periodic faces must come in pairs");
@@ -111,10 +120,11 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   L->pop_bytes = (size_t)Q * N * pop_elem(p->precision);
   L->scal_bytes = (size_t)NS * N * scal_elem(p->precision);
   L->off_flag = 0;
-  L->off_sums = 64;
+  L->off_sums = 64;                       // NSUM doubles
+  L->off_thermo = 192;                    // 3 doubles
   L->off_stage = 256;
-  L->off_partials = L->off_stage + 256 * 8 * sizeof(double);
-  L->off_geom = align256(L->off_partials + (size_t)L->nblocks * 8 * sizeof(double));
+  L->off_partials = L->off_stage + 256 * NSUM * sizeof(double);
+  L->off_geom = align256(L->off_partials + (size_t)L->nblocks * NSUM * sizeof(double));
   L->work_bytes = align256(L->off_geom + (size_t)N * (Q == 9 ? 4 : 8));
   return LBM_OK;
 }
@@ -131,6 +141,8 @@ static StepArgs make_args(const lbm_solver *s) {
   a.geom = s->has_geom ? s->geom : nullptr;
   a.partials = s->partials;
   a.flag = s->flag;
+  a.thermo = s->closed ? s->thermo : nullptr;
+  a.kappa = s->closed ? (p.gamma - 1.0) / p.gamma : 0.0;
   a.nx = p.nx;
   a.ny = p.ny;
   a.nz = p.nz;
@@ -238,8 +250,11 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
   s->sums = (double *)(s->work + L.off_sums);
   s->partials = (double *)(s->work + L.off_partials);
   s->stage = (double *)(s->work + L.off_stage);
+  s->thermo = (double *)(s->work + L.off_thermo);
+  s->closed = p->pth_mode == LBM_PTH_CLOSED;
   s->geom = s->work + L.off_geom;
   hipError_t e = hipMemsetAsync(s->work, 0, 256, s->stream);
+  if (e == hipSuccess) e = launch_set_thermo(s->thermo, 1.0, 0.0, 0.0, s->stream);
   if (e != hipSuccess) {
     g_create_err = std::string("clearing the work buffer: ") + hipGetErrorString(e);
     delete s;
@@ -274,6 +289,8 @@ lbm_status lbm_init_fields(lbm_solver *s, const double *P_h, const double *u, co
   a.scal_out = s->scal[s->cur];
   hipError_t e = launch(s, LAUNCH_INIT, a, P_h, u, scal);
   if (e != hipSuccess) return hip_fail(s, e, "init kernel");
+  e = launch_set_thermo(s->thermo, 1.0, 0.0, 0.0, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "resetting the thermodynamic pressure");
   e = hipMemsetAsync(s->flag, 0, sizeof(int), s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "clearing the divergence flag");
   s->initialized = true;
@@ -299,6 +316,10 @@ lbm_status lbm_step(lbm_solver *s, int32_t nsteps) {
     a.step = s->step;
     hipError_t e = launch(s, LAUNCH_STEP, a);
     if (e != hipSuccess) return hip_fail(s, e, "step kernel");
+    if (s->closed) {
+      e = launch_finalize(s->partials, s->nblocks, s->stage, s->sums, s->stream, s->thermo);
+      if (e != hipSuccess) return hip_fail(s, e, "thermodynamic pressure update");
+    }
     s->cur ^= 1;
     s->step += 1;
   }
@@ -312,6 +333,10 @@ lbm_status lbm_step_from(lbm_solver *s, const void *pops_in, const void *scal_in
       (s->NS > 0 && (!scal_in || !scal_out || scal_in == scal_out))) {
     s->err = "lbm_step_from: distinct input and output buffers are required";
     return LBM_E_INVALID;
+  }
+  if (s->closed) {
+    s->err = "lbm_step_from: a closed domain carries its thermodynamic pressure in the solver";
+    return LBM_E_UNSUPPORTED;
   }
   StepArgs a = make_args(s);
   a.pop_in = pops_in;
@@ -382,6 +407,26 @@ lbm_status lbm_set_state(lbm_solver *s, const void *pops_src, const void *scal_s
   return LBM_OK;
 }
 
+lbm_status lbm_get_thermo_pressure(lbm_solver *s, double *pqk_host) {
+  if (!s || !pqk_host) return LBM_E_INVALID;
+  hipError_t e = hipMemcpyAsync(pqk_host, s->thermo, 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "reading the thermodynamic pressure");
+  return LBM_OK;
+}
+
+lbm_status lbm_set_thermo_pressure(lbm_solver *s, const double *pqk_host) {
+  if (!s || !pqk_host) return LBM_E_INVALID;
+  if (!(pqk_host[0] > 0.0) || !isfinite(pqk_host[0]) || !isfinite(pqk_host[1]) || !(pqk_host[2] >= 0.0) ||
+      !isfinite(pqk_host[2])) {
+    s->err = "thermodynamic pressure: pi > 0, finite q, K >= 0 required";
+    return LBM_E_INVALID;
+  }
+  hipError_t e = launch_set_thermo(s->thermo, pqk_host[0], pqk_host[1], pqk_host[2], s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "setting the thermodynamic pressure");
+  return LBM_OK;
+}
+
 const char *lbm_last_error(const lbm_solver *s) { return s ? s->err.c_str() : g_create_err.c_str(); }
 
 void lbm_destroy(lbm_solver *s) { delete s; }
@@ -398,6 +443,7 @@ static lbm_status adjoint_supported(lbm_solver *s) {
   else if (p.omega_high != 1.0) why = "the adjoint needs omega_high == 1";
   else if (p.precision == LBM_FP16S) why = "the adjoint runs in FP64 or FP32";
   else if (s->has_geom) why = "the adjoint covers domains without solid cells";
+  else if (s->closed) why = "the adjoint covers a constant thermodynamic pressure";
   else
     for (int f = 0; f < 6; ++f)
       if (p.face_bc[f] != LBM_PERIODIC) why = "the adjoint covers periodic domains";

@@ -24,11 +24,17 @@ hipError_t launch_geometry(int Q, const uint8_t *solid, void *geom, int nx, int 
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *partials, int nblocks, double *stage, double *out, hipStream_t st) {
+hipError_t launch_finalize(const double *partials, int nblocks, double *stage, double *out, hipStream_t st,
+                           double *thermo) {
   const int nb1 = nblocks < 256 ? nblocks : 256;
   const int chunk = (nblocks + nb1 - 1) / nb1;
-  hipLaunchKernelGGL(finalize_stage, dim3(nb1), dim3(256), 0, st, partials, nblocks, chunk, stage);
-  hipLaunchKernelGGL(finalize_stage, dim3(1), dim3(256), 0, st, (const double *)stage, nb1, nb1, out);
+  hipLaunchKernelGGL(finalize_stage, dim3(nb1), dim3(256), 0, st, partials, nblocks, chunk, stage, (double *)nullptr);
+  hipLaunchKernelGGL(finalize_stage, dim3(1), dim3(256), 0, st, (const double *)stage, nb1, nb1, out, thermo);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_thermo(double *thermo, double pi, double q, double K, hipStream_t st) {
+  hipLaunchKernelGGL(set_thermo_kernel, dim3(1), dim3(64), 0, st, thermo, pi, q, K);
   return hipGetLastError();
 }
 }  // namespace lbm

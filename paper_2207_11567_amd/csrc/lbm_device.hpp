@@ -323,12 +323,13 @@ template <class R> struct ThermoT {
 };
 
 
+// Ideal-gas density at the thermodynamic pressure pi P_th(0) (pi = 1 in open domains).
 template <int NS, class R>
-__device__ __forceinline__ R density(const ThermoT<R> &t, const R (&v)[NS > 0 ? NS : 1]) {
+__device__ __forceinline__ R density(const ThermoT<R> &t, const R (&v)[NS > 0 ? NS : 1], R pi = R(1)) {
   if constexpr (NS <= 1) {
     return t.rho_ref;
   } else if constexpr (NS == 2) {
-    return fdiv(t.rhoT, v[0]);
+    return fdiv(t.rhoT * pi, v[0]);
   } else {
     // rho = rho_ref (T_ref/T)(W/W_ref), 1/W = sum Y_k/W_k with N2 by closure
     R ysum = R(0), inv = R(0);
@@ -338,7 +339,7 @@ __device__ __forceinline__ R density(const ThermoT<R> &t, const R (&v)[NS > 0 ? 
       inv += v[1 + k] * t.inv_W[k];
     }
     inv += (R(1) - ysum) * t.inv_W[5];
-    return fdiv(t.rhoT_W, v[0] * inv);
+    return fdiv(t.rhoT_W * pi, v[0] * inv);
   }
 }
 

@@ -20,7 +20,11 @@ hipError_t launch_geometry(int Q, const uint8_t *solid, void *geom, int nx, int 
 // 3: reverse of the initialisation (p0 lamA, p1 lamT, u0, gu out, p3 grad T out).
 hipError_t launch_adjoint(int prec, int ns, int kind, const StepArgs &sa, int nblocks, hipStream_t st, const void *p0,
                           const void *p1, void *p2, void *p3, void *p4, double mean_T, const double *u0, double *gu);
-hipError_t launch_finalize(const double *partials, int nblocks, double *stage, double *out, hipStream_t st);
+// Sums of the per-block records into out[NSUM]; with thermo (closed domain) also the
+// thermodynamic pressure of the next level.
+hipError_t launch_finalize(const double *partials, int nblocks, double *stage, double *out, hipStream_t st,
+                           double *thermo = nullptr);
+hipError_t launch_set_thermo(double *thermo, double pi, double q, double K, hipStream_t st);
 
 template <int Q, int PREC, int NS>
 hipError_t launch_one(int kind, const StepArgs &a, int nblocks, hipStream_t st, const double *Ph,

@@ -9,6 +9,10 @@
 //   -> source Xi (Eq. 2) -> pre-conditioning (Eq. 13) -> cumulant collision (Eqs. 9-12)
 //   -> post-collision populations (Eq. 8) stored as deviations from the lattice weights
 //   -> FP64 block partial sums (wavefront shuffles + LDS), one record per block.
+// In a closed domain the thermodynamic pressure P_th = pi P_th(0) scales the ideal-gas
+// density, its rate q = dln(pi)/dt adds the pressure work kappa T q to the temperature
+// right-hand side and shifts Lambda to the velocity divergence Lambda - q, and the
+// finalisation of the sums sets pi for the next step from the mass the domain holds.
 #pragma once
 
 #include <type_traits>
@@ -16,6 +20,10 @@
 #include "lbm_device.hpp"
 
 namespace lbm {
+
+// Per-block FP64 sums: rho, P_h, rho u (3), rho |u|^2/2, W/T, rho Y_1 at level n, and
+// W/T of the updated scalars (level n+1; formed in closed domains only).
+constexpr int NSUM = 9;
 
 // Host-side description of one launch (double precision constants).
 struct Thermo {
@@ -29,8 +37,10 @@ struct StepArgs {
   const void *scal_in;
   void *scal_out;
   const void *geom;    // per-cell geometry words or nullptr
-  double *partials;    // [nblocks][8]
+  double *partials;    // [nblocks][NSUM]
   int *flag;           // bit 0: non-finite value seen
+  const double *thermo;  // closed domain: device (pi, q, K); nullptr when P_th is constant
+  double kappa;        // (gamma - 1)/gamma
   double *f_P, *f_rho, *f_u, *f_scal;   // field outputs (extract mode)
   int nx, ny, nz;
   long long N;
@@ -58,12 +68,13 @@ template <class R> struct KArgs {
   const void *geom;
   double *partials;
   int *flag;
+  const double *thermo;
   double *f_P, *f_rho, *f_u, *f_scal;
   int nx, ny, nz, N;
   int face[6];
   long long step;
   int collision, remap, band_rows;
-  R P0, invP0, wb, wh, smag18;
+  R P0, invP0, wb, wh, smag18, kap;
   R inlet_u[3], outlet_P;
   double inlet_noise;
   R phi_in[8], eps[8];
@@ -75,7 +86,8 @@ template <class R> struct KArgs {
 template <class R> KArgs<R> to_kargs(const StepArgs &a) {
   KArgs<R> k;
   k.pop_in = a.pop_in; k.pop_out = a.pop_out; k.scal_in = a.scal_in; k.scal_out = a.scal_out;
-  k.geom = a.geom; k.partials = a.partials; k.flag = a.flag;
+  k.geom = a.geom; k.partials = a.partials; k.flag = a.flag; k.thermo = a.thermo;
+  k.kap = (R)a.kappa;
   k.f_P = a.f_P; k.f_rho = a.f_rho; k.f_u = a.f_u; k.f_scal = a.f_scal;
   k.nx = a.nx; k.ny = a.ny; k.nz = a.nz; k.N = (int)a.N;
   for (int f = 0; f < 6; ++f) k.face[f] = a.face[f];
@@ -175,17 +187,18 @@ template <class T> __device__ __forceinline__ void stg_nt(T *base, unsigned idx,
 }
 
 
-// Block reduction of 8 doubles into partials[tile*8 ..] in a fixed order: every thread
-// parks its values in LDS, then lane t of wave 0 sums 32 cells of counter t/8, and the 8
-// lanes of each counter combine by xor-shuffles.  256 threads per block.
-__device__ __forceinline__ void block_sums(double (&v)[8], double *out) {
-  __shared__ double sh[8][256];
+// Block reduction of NSUM doubles into partials[tile*NSUM ..] in a fixed order: every
+// thread parks its values in LDS, then thread t < 8 NSUM sums 32 cells of counter t/8, and
+// the 8 threads of each counter (aligned groups inside one wave) combine by xor-shuffles.
+// 256 threads per block.
+__device__ __forceinline__ void block_sums(double (&v)[NSUM], double *out) {
+  __shared__ double sh[NSUM][256];
   const int t = threadIdx.x;
   const int slot = (t & 31) * 8 + (t >> 5);          // part (t>>5) of 8, element t&31
 #pragma unroll
-  for (int k = 0; k < 8; ++k) sh[k][slot] = v[k];
+  for (int k = 0; k < NSUM; ++k) sh[k][slot] = v[k];
   __syncthreads();
-  if (t < 64) {
+  if (t < 8 * NSUM) {
     const int k = t >> 3, part = t & 7;
     double acc = 0.0;
 #pragma unroll 8
@@ -194,6 +207,23 @@ __device__ __forceinline__ void block_sums(double (&v)[8], double *out) {
     acc += __shfl_xor(acc, 2, 64);
     acc += __shfl_xor(acc, 1, 64);
     if (part == 0) out[k] = acc;
+  }
+}
+
+// W/T of a cell up to a constant factor (the density per unit thermodynamic pressure):
+// 1/T_ref without a temperature, 1/T for the one-step model's constant W.
+template <int NS, class R>
+__device__ __forceinline__ double w_over_T(const ThermoT<R> &t, const R (&v)[NS > 0 ? NS : 1], double inv_T_ref) {
+  if constexpr (NS <= 1) {
+    return inv_T_ref;
+  } else if constexpr (NS == 2) {
+    return (double)fdiv(R(1), v[0]);
+  } else {
+    R ys = R(0), inv = R(0);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) { ys += v[1 + q]; inv += v[1 + q] * t.inv_W[q]; }
+    inv += (R(1) - ys) * t.inv_W[5];
+    return (double)fdiv(R(1), inv * v[0]);
   }
 }
 
@@ -225,7 +255,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
   } else {
     n = tile * (int)blockDim.x + (int)threadIdx.x;
   }
-  double red[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double red[NSUM] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int N = a.N;
   const unsigned un = (unsigned)n;
   const St *__restrict__ pin = (const St *)a.pop_in;
@@ -289,13 +319,19 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
       };
 
       // ---------------------------------------------------------------- cell scalars, rho
+      // closed domain: density scaled by pi = P_th/P_th(0); q = dln(pi)/dt of this level
+      R pim = R(1), qn = R(0);
+      if (a.thermo) {
+        pim = (R)a.thermo[0];
+        qn = (R)a.thermo[1];
+      }
       R phi0[NSV], phin[NSV];
 #pragma unroll
       for (int k = 0; k < NSV; ++k) { phi0[k] = R(0); phin[k] = R(a.phi_in[k]); }
 #pragma unroll
       for (int k = 0; k < NS; ++k) phi0[k] = (R)ldg(sin_ + (size_t)k * N, un);
-      const R rho0 = NS > 0 ? density<NS, R>(a.th, phi0) : R(a.th.rho_ref);
-      const R rho_in = NS > 0 ? density<NS, R>(a.th, phin) : R(a.th.rho_ref);
+      const R rho0 = NS > 0 ? density<NS, R>(a.th, phi0, pim) : R(a.th.rho_ref);
+      const R rho_in = NS > 0 ? density<NS, R>(a.th, phin, pim) : R(a.th.rho_ref);
 
       // ---------------------------------------------------------------- pull (Eq. 1)
       R gh[Q];
@@ -426,8 +462,8 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             }
             // density at +-1 and diffusion through the two faces
             R rp = rho0, rm = rho0;
-            if (FAST || sp1 == ST_FLUID) rp = density<NS, R>(a.th, vp1); else if (sp1 == ST_INLET) rp = rho_in;
-            if (FAST || sm1 == ST_FLUID) rm = density<NS, R>(a.th, vm1); else if (sm1 == ST_INLET) rm = rho_in;
+            if (FAST || sp1 == ST_FLUID) rp = density<NS, R>(a.th, vp1, pim); else if (sp1 == ST_INLET) rp = rho_in;
+            if (FAST || sm1 == ST_FLUID) rm = density<NS, R>(a.th, vm1, pim); else if (sm1 == ST_INLET) rm = rho_in;
             gradrho[d] = R(0.5) * (rp - rm);
             // face coefficients: arithmetic mean of rho D (uniform when rho nu is constant)
             R cfp, cfm;
@@ -480,7 +516,9 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           const R r = a.th.B1 * fmax(phi0[1], R(0)) * exp(-fdiv(a.th.Ta1, phi0[0]));
           R_s[0] += a.th.heat1 * r * invF;
           R_s[1] -= r * invF;
+          if (a.thermo) R_s[0] += a.kap * qn * phi0[0];   // pressure work
           Lam = fdiv(R_s[0], phi0[0]);
+          if (a.thermo) Lam -= qn;                        // div u = Lambda - dln(pi)/dt
         } else if constexpr (NS == 6) {
           R conc[5];
 #pragma unroll
@@ -501,6 +539,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           const R heat = -(a.th.h[0] * m0 + a.th.h[1] * m1 + a.th.h[2] * m2 + a.th.h[3] * m3 +
                            a.th.h[4] * m4) * a.th.inv_cp;
           R_s[0] += heat * invF;
+          if (a.thermo) R_s[0] += a.kap * qn * T;         // pressure work
           // Lambda = R_T/T + W sum_k R_k/W_k (N2 by closure: R_N2 = -sum R_k)
           R ysum = R(0), invW = R(0), acc = R(0), rsum = R(0);
 #pragma unroll
@@ -513,6 +552,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           invW += (R(1) - ysum) * a.th.inv_W[5];
           acc -= rsum * a.th.inv_W[5];
           Lam = R_s[0] * iT + fdiv(acc, invW);
+          if (a.thermo) Lam -= qn;                        // div u = Lambda - dln(pi)/dt
         }
       }
       const R Ph = P0 * (sg + R(1)) + R(0.5) * rho0 * s * Lam;   // Eq. 7a
@@ -529,12 +569,16 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
       } else {
         // ------------------------------------------------------------ scalar update
         bool bad = false;
+        R phi1[NSV];
+        phi1[0] = R(0);
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
           const R nv = phi0[q] + (R_s[q] - adv[q]);
           bad |= !isfinite(nv);
           stg(sout + (size_t)q * N, un, (Sc)nv);
+          phi1[q] = (R)(Sc)nv;
         }
+        if (a.thermo) red[8] = w_over_T<NS>(a.th, phi1, a.inv_T_ref_d);
         // ------------------------------------------------------------ collision
         const R r = fdiv(a.th.rho_ref, rho0);           // P0/(rho cs2)
         const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -617,46 +661,60 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
       red[3] = rd * (double)u[1];
       red[4] = rd * (double)u[2];
       red[5] = 0.5 * rd * ((double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]);
-      if constexpr (NS <= 1) {
-        red[6] = a.inv_T_ref_d;
-      } else if constexpr (NS == 2) {
-        red[6] = (double)fdiv(R(1), phi0[0]);
-      } else {
-        R ys = R(0), inv = R(0);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) { ys += phi0[1 + q]; inv += phi0[1 + q] * a.th.inv_W[q]; }
-        inv += (R(1) - ys) * a.th.inv_W[5];
-        red[6] = (double)fdiv(R(1), inv * phi0[0]);
-      }
+      red[6] = w_over_T<NS>(a.th, phi0, a.inv_T_ref_d);
       if constexpr (NS >= 2) red[7] = rd * (double)phi0[1];
     }
   }
-  block_sums(red, a.partials + (size_t)tile * 8);
+  block_sums(red, a.partials + (size_t)tile * NSUM);
 }
 
 
 // Deterministic reduction of the per-block records: stage 1 gives each of up to 256
 // blocks a contiguous range of records, stage 2 sums the stage-1 records in one block.
 // The order of every addition is fixed by the launch shape, so results are bitwise
-// repeatable.
-static __global__ __launch_bounds__(256) void finalize_stage(const double *in, int nrec, int chunk, double *out) {
-  __shared__ double sh[8][256];
+// repeatable.  Given thermo (closed domain, stage 2 only), the final sums also advance
+// (pi, q, K): K = pi sum W/T at the first step, pi' = K / sum W/T of the updated
+// scalars (the total mass is held), q' = (pi' - pi)/pi.
+static __global__ __launch_bounds__(256) void finalize_stage(const double *in, int nrec, int chunk, double *out,
+                                                             double *thermo) {
+  __shared__ double sh[NSUM][256];
   const int b0 = blockIdx.x * chunk;
   const int b1 = min(nrec, b0 + chunk);
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[NSUM];
+#pragma unroll
+  for (int k = 0; k < NSUM; ++k) acc[k] = 0.0;
   for (int b = b0 + (int)threadIdx.x; b < b1; b += 256)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] += in[(size_t)b * 8 + k];
+    for (int k = 0; k < NSUM; ++k) acc[k] += in[(size_t)b * NSUM + k];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] = acc[k];
+  for (int k = 0; k < NSUM; ++k) sh[k][threadIdx.x] = acc[k];
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+      for (int k = 0; k < NSUM; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x < 8) out[(size_t)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x < NSUM) out[(size_t)blockIdx.x * NSUM + threadIdx.x] = sh[threadIdx.x][0];
+  if (thermo && threadIdx.x == 0) {
+    const double pi = thermo[0];
+    double K = thermo[2];
+    if (!(K > 0.0)) K = pi * sh[6][0];
+    const double pn = K / sh[8][0];
+    thermo[0] = pn;
+    thermo[1] = (pn - pi) / pi;
+    thermo[2] = K;
+  }
+}
+
+// (pi, q, K) set from the host's values (a kernel rather than a copy, so that the call
+// needs no host buffer to outlive it).
+static __global__ void set_thermo_kernel(double *thermo, double pi, double q, double K) {
+  if (threadIdx.x == 0) {
+    thermo[0] = pi;
+    thermo[1] = q;
+    thermo[2] = K;
+  }
 }
 
 // Geometry words from a solid mask (see GeomWord).

@@ -108,6 +108,16 @@ class Solver:
         self._chk(C.lib().lbm_step_sums(self._h, sums))
         return list(sums)
 
+    def thermo_pressure(self):
+        """(pi, q, K): P_th/P_th(0), its logarithmic rate per step, the held mass constant."""
+        v = (ctypes.c_double * 3)()
+        self._chk(C.lib().lbm_get_thermo_pressure(self._h, v))
+        return tuple(v)
+
+    def set_thermo_pressure(self, pqk):
+        v = (ctypes.c_double * 3)(*[float(x) for x in pqk])
+        self._chk(C.lib().lbm_set_thermo_pressure(self._h, v))
+
     def get_state(self):
         pops = torch.empty((self.Q,) + self.shape, dtype=self.pop_dtype, device=self.device)
         scal = torch.empty((self.NS,) + self.shape, dtype=self.scal_dtype, device=self.device)

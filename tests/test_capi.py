@@ -35,6 +35,9 @@ def test_exports_every_declared_symbol():
     ({"omega_bulk": 2.5}, "omega_bulk"),
     ({"face_bc": ["periodic", "wall", "periodic", "periodic", "periodic", "periodic"]}, "pairs"),
     ({"physics": "passive", "nu_ref": 0.4}, "unstable"),
+    ({"pth_mode": "closed", "face_bc": ["inlet", "outlet", "wall", "wall", "periodic", "periodic"]},
+     "closed domain"),
+    ({"pth_mode": "closed", "gamma": 1.0}, "gamma"),
 ])
 def test_validation_rejects(change, needle):
     C, lib = _lib()
@@ -54,4 +57,4 @@ def test_sizes_of_valid_parameters():
                                ctypes.byref(wb)) == C.LBM_OK
     N = 16 * 16 * 32
     assert pb.value == 27 * N * 4 and sb.value == 6 * N * 4
-    assert wb.value >= N * 8 + (N // 256) * 64
+    assert wb.value >= N * 8 + (N // 256) * 72
