@@ -10,7 +10,7 @@ FACE_CODES = {"periodic": None, "wall": SOLID, "inlet": INLET, "outlet": OUTLET}
 
 
 class Grid:
-    def __init__(self, params, solid=None):
+    def __init__(self, params, solid=None, phi=None):
         self.nx, self.ny, self.nz = params["nx"], params["ny"], params["nz"]
         self.shape = (self.nz, self.ny, self.nx)
         self.D = 2 if params["lattice"] == "D2Q9" else 3
@@ -19,6 +19,8 @@ class Grid:
             solid = torch.zeros(self.shape, dtype=torch.bool)
         self.solid = solid.to(torch.bool).reshape(self.shape)
         self.fluid = ~self.solid
+        # signed wall distance at the nodes (curved walls), or None (staircase walls)
+        self.phi = None if phi is None else phi.to(torch.float64).reshape(self.shape)
         idx = torch.meshgrid(torch.arange(self.nz), torch.arange(self.ny),
                              torch.arange(self.nx), indexing="ij")
         self.coord = [idx[2], idx[1], idx[0]]          # x, y, z index of every cell
@@ -50,6 +52,11 @@ class Grid:
             if fc is not None:
                 code = torch.where(mask, torch.full_like(code, fc), code)
         return code >= 0, code
+
+    def solid_cell(self, d, k):
+        """Position i + k e_d is a solid cell inside the domain (not beyond a face)."""
+        outside, _ = self.face_of(d, k)
+        return self.shift(self.solid, d, k) & ~outside
 
     def status(self, d, k):
         """Classification of position i + k e_d for every cell i."""

@@ -23,6 +23,7 @@ Readings (the paper defers the coupling details to earlier work):
 """
 import torch
 
+from . import curved
 from .grid import FLUID, INLET, OUTLET, SOLID
 
 
@@ -95,7 +96,34 @@ def stencil(grid, phi, d, phi_in):
         beyond = torch.where(s2 == FLUID, raw[2 * k], torch.where(s2 == INLET, pin, v[k]))
         ghost = torch.where(s1 == SOLID, v[-k], torch.where(s1 == INLET, pin, v0))
         v[2 * k] = torch.where(s1 == FLUID, beyond, ghost)
+    if grid.phi is not None:
+        v = _curved_ghosts(grid, d, v, raw, st)
     return v
+
+
+def _curved_ghosts(grid, d, v, raw, st):
+    """Mirror-image ghosts about curved walls (module curved) for stencil points that are
+    solid cells; faces and cells without a fluid line behind them keep the plain rule."""
+    out = dict(v)
+    phi = grid.phi
+    for k in (1, -1):
+        cell1, cell2 = grid.solid_cell(d, k), grid.solid_cell(d, 2 * k)
+        back1 = st[-k] == FLUID
+        back2 = st[-2 * k] == FLUID
+        # wall between node 0 and node k
+        q1 = curved.fraction(phi, torch.where(cell1, grid.shift(phi, d, k), phi - 1.0))
+        g1 = curved.mirror_value(1.0 - 2.0 * q1, v[0], raw[-k], raw[-2 * k])
+        p2 = 2.0 - 2.0 * q1
+        g2 = curved.mirror_value(p2, v[0], raw[-k], raw[-2 * k])
+        ok1 = cell1 & back1
+        out[k] = torch.where(ok1, g1, out[k])
+        out[2 * k] = torch.where(ok1 & ((p2 <= 1.0) | back2), g2, out[2 * k])
+        # wall between node k (fluid) and node 2k
+        pk = grid.shift(phi, d, k)
+        q2 = curved.fraction(pk, torch.where(cell2, grid.shift(phi, d, 2 * k), pk - 1.0))
+        g3 = curved.mirror_value(1.0 - 2.0 * q2, raw[k], v[0], v[0])
+        out[2 * k] = torch.where((st[k] == FLUID) & cell2, g3, out[2 * k])
+    return out
 
 
 def weno3_face(a, b, c, eps):
@@ -125,6 +153,28 @@ def diffusion(grid, phi, rhoD, d, phi_in, rhoD_in):
         flux_i = 0.5 * (rhoD + rhoD_in) * (phi_in - phi)
         out = out + torch.where(s == FLUID, flux_f, torch.where(s == INLET, flux_i, 0.0))
     return out
+
+
+def density_gradient(params, grid, scal, rho, rho_in, pth=1.0):
+    """Central differences of the density; with curved walls the ghost of a solid cell
+    is the ideal-gas density of the ghost scalars (module curved), else as gradient()."""
+    if grid.phi is None:
+        return gradient(grid, rho, rho_in)
+    S = n_scalars(params)
+    phin = inlet_scalars(params)
+    out = []
+    for d in range(grid.D):
+        st = [stencil(grid, scal[s], d, phin[s]) for s in range(S)]
+        vals = []
+        for k in (1, -1):
+            s = grid.status(d, k)
+            ghost_scal = torch.stack([st[q][k] for q in range(S)])
+            rho_ghost = density(params, ghost_scal, grid.shape, pth)
+            plain = torch.where(s == FLUID, grid.shift(rho, d, k),
+                                torch.where(s == INLET, torch.full_like(rho, rho_in), rho))
+            vals.append(torch.where(grid.solid_cell(d, k), rho_ghost, plain))
+        out.append(0.5 * (vals[0] - vals[1]))
+    return torch.stack(out)
 
 
 def gradient(grid, f, f_in):

@@ -21,11 +21,12 @@ u_w = u_in (1 + a xi) and xi the counter-based noise; beyond an outlet face it i
 anti-bounce-back pressure condition, g_i(r) = -g*_opp(i)(r) + 2 w_i [P_out +
 rho ((c_i . u_w)^2/(2 cs2) - u_w^2/2)] with rho = rho^n(r) and u_w the momentum of the
 cell's own post-collision populations.  A link leaving through several faces takes the
-first of wall, inlet, outlet.  Periodic faces wrap.
+first of wall, inlet, outlet.  Periodic faces wrap.  With a signed wall distance phi
+(curved walls, module curved) links from solid cells use the interpolated bounce-back.
 """
 import torch
 
-from . import cumulant, equations, noise, pressure, scalars
+from . import cumulant, curved, equations, noise, pressure, scalars
 from .grid import INLET, OUTLET, SOLID, Grid
 from .lattice import CS2, get as get_lattice
 
@@ -81,6 +82,16 @@ def pull(params, lat, grid, A, rho, n):
             inl |= outside & (code == INLET)
             outl |= outside & (code == OUTLET)
         opp = A[int(lat.opp[i])]
+        val_solid = opp
+        if grid.phi is not None:
+            phi_src = grid.shift_vec(grid.phi, offs)
+            q = curved.fraction(grid.phi, torch.where(solid_src, phi_src, grid.phi - 1.0))
+            ahead = [c[d] for d in range(D)] + [0] * (3 - D)            # r + c_i
+            nxt_fluid = ~grid.shift_vec(grid.solid, ahead)
+            for d in range(D):
+                if c[d]:
+                    nxt_fluid &= ~grid.face_of(d, c[d])[0]
+            val_solid = curved.bounce_back(q, opp, grid.shift_vec(opp, ahead), A[i], nxt_fluid)
         cu_in = sum(c[d] * u_in[d] for d in range(D))
         cu_out = sum(c[d] * u_out[d] for d in range(D))
         val_bb = opp
@@ -89,25 +100,30 @@ def pull(params, lat, grid, A, rho, n):
         g[i] = torch.where(wall, val_bb,
                            torch.where(inl, val_in,
                                        torch.where(outl, val_out,
-                                                   torch.where(solid_src, val_bb, src))))
+                                                   torch.where(solid_src, val_solid, src))))
     return g
 
 
-def _grid_of(params, solid):
-    return Grid(params, solid)
+def _grid_of(params, solid, phi=None):
+    return Grid(params, solid, phi)
 
 
-def init_state(params, P_h, u, scal, solid=None):
+def init_state(params, P_h, u, scal, solid=None, phi=None):
     """Populations at the equilibrium of Eq. 6 for the given fields (no non-equilibrium
-    part): g*(-1) := g_eq(P_h, rho(T, Y), u).  Fields are (nz, ny, nx) / (D, nz, ny, nx)."""
+    part): g*(-1) := g_eq(P_h, rho(T, Y), u).  Fields are (nz, ny, nx) / (D, nz, ny, nx).
+    phi (optional): signed wall distance at the nodes for curved walls; the solid cells are
+    then phi < 0."""
     lat = get_lattice(params["lattice"])
-    grid = _grid_of(params, solid)
+    if phi is not None:
+        phi = phi.to(torch.float64)
+        solid = phi < 0
+    grid = _grid_of(params, solid, phi)
     scal = scal.to(torch.float64) if scal is not None else torch.zeros((0,) + grid.shape,
                                                                        dtype=torch.float64)
     rho = scalars.density(params, scal, grid.shape)
     A = equations.g_eq(lat, P_h.to(torch.float64), rho, u.to(torch.float64))
     return {"pops": A, "scal": scal.clone(), "step": 0, "solid": grid.solid,
-            "thermo": pressure.initial()}
+            "thermo": pressure.initial(), "phi": phi}
 
 
 def _thermo(state):
@@ -117,7 +133,7 @@ def _thermo(state):
 def _level_n(params, state):
     """Everything the step computes at level n before collision."""
     lat = get_lattice(params["lattice"])
-    grid = _grid_of(params, state["solid"])
+    grid = _grid_of(params, state["solid"], state.get("phi"))
     scal = state["scal"]
     thermo = _thermo(state)
     rho = scalars.density(params, scal, grid.shape, thermo[0])
@@ -128,7 +144,7 @@ def _level_n(params, state):
     if params["physics"] in ("one_step", "two_step"):
         rho_in = scalars.density(params, scalars.inlet_scalars(params).reshape(-1, 1, 1, 1),
                                  (1, 1, 1)).reshape(())
-        grad_rho = scalars.gradient(grid, rho, float(rho_in))
+        grad_rho = scalars.density_gradient(params, grid, scal, rho, float(rho_in), thermo[0])
     else:
         grad_rho = torch.zeros((grid.D,) + grid.shape, dtype=torch.float64)
     return lat, grid, rho, g, R, Lam, P_h, u, grad_rho
@@ -181,7 +197,7 @@ def step(params, state):
     if pressure.closed(params):
         thermo = pressure.update(thermo, float(sums[6]), _w_over_T_sum(params, grid, new_scal))
     return ({"pops": gs, "scal": new_scal, "step": state["step"] + 1,
-             "solid": state["solid"], "thermo": thermo}, sums)
+             "solid": state["solid"], "thermo": thermo, "phi": state.get("phi")}, sums)
 
 
 def fields(params, state):
