@@ -54,6 +54,12 @@ def workload(name, precision=None):
         p, P, u = L.hit(256)
         s, solid = None, None
         desc = "decaying isotropic turbulence 256^3 D3Q27, Smagorinsky 0.17"
+    elif name in ("chamber2d", "chamber2d_open"):
+        closed = name == "chamber2d"
+        p, P, u, s, solid = L.chamber2d(closed=closed)
+        desc = ("deflagration chamber 2500x500 D2Q9 (Sec. 3.1 geometry), 1-step Arrhenius, F=4, "
+                + ("closed: thermodynamic pressure from the held mass" if closed else
+                   "walls, constant thermodynamic pressure"))
     elif name == "tgv":
         p, P, u = L.tgv(128)
         s, solid = None, None
@@ -86,7 +92,7 @@ def run_gpu(name, steps, warmup, precision=None):
     p, P, u, s, solid, desc = workload(name, precision)
     solver = Solver(p, device="cuda:0")
     if solid is not None:
-        solver.set_geometry(torch.from_numpy(solid))
+        solver.set_geometry(torch.from_numpy(solid.astype(np.uint8)))
     solver.init_fields(torch.from_numpy(P), torch.from_numpy(u),
                        torch.from_numpy(s) if s is not None else None)
     del P, u, s
@@ -263,7 +269,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="reacting_box",
-                    choices=["reacting_box", "flame2d", "hit", "tgv", "passive_box"])
+                    choices=["reacting_box", "flame2d", "hit", "tgv", "passive_box", "chamber2d",
+                             "chamber2d_open"])
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "fp16s"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
@@ -309,7 +316,8 @@ def main():
     if not args.no_extra:
         for name, prec, k in (("tgv", "fp64", 1000), ("flame2d", "fp64", 400),
                               ("flame2d", "fp32", 400), ("hit", "fp64", 40), ("hit", "fp32", 60),
-                              ("hit", "fp16s", 60), ("passive_box", "fp32", 100)):
+                              ("hit", "fp16s", 60), ("passive_box", "fp32", 100),
+                              ("chamber2d", "fp64", 400), ("chamber2d_open", "fp64", 400)):
             r = run_gpu(name, k, 10, prec)
             extra[f"{name}_{prec}"] = {"mlups": round(r["mlups"], 1),
                                        "ms_per_step": round(r["ms_per_step"], 4),

@@ -122,6 +122,22 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
  * zero-flux scalars; NULL clears the geometry.  The mask is read once here. */
 lbm_status lbm_set_geometry(lbm_solver *s, const uint8_t *solid_dev);
 
+/* Curved walls (the paper's treatment of curved boundaries for both solvers, Sec. 1 and
+ * Sec. 3; methods not given, read as below).  phi_dev: device FP64 [nz][ny][nx], the
+ * signed wall distance at the nodes (>= 0 fluid, < 0 solid, in cells); the solid cells are
+ * phi < 0 and, along a link or grid line from a fluid node r to a solid node s, the wall
+ * lies at the fraction q = phi(r)/(phi(r) - phi(s)) of the way.  Populations arriving from
+ * a solid node take the linearly interpolated bounce-back of Bouzidi, Firdaouss and
+ * Lallemand (2001): q < 1/2: g_i(r) = 2q g*_ib(r) + (1-2q) g*_ib(r+c_i) (halfway if
+ * r + c_i is not fluid); q >= 1/2: g_i(r) = g*_ib(r)/(2q) + (1 - 1/(2q)) g*_i(r).  Scalar
+ * stencil points in solid cells take the value at their mirror image about the wall on
+ * the grid line (linear interpolation between fluid nodes; an image between the wall and
+ * the first node takes the even quadratic through the two nearest nodes), the density
+ * there is the ideal gas of those values, and diffusion fluxes through solid faces stay
+ * zero.  Domain faces keep the halfway rules.  The library keeps phi_dev (the caller keeps
+ * it alive until the next geometry call); NULL clears the geometry. */
+lbm_status lbm_set_wall_distance(lbm_solver *s, const double *phi_dev);
+
 /* Equilibrium initialisation (Eq. 6): post-collision populations of level -1 are set to
  * g_eq(P_h, rho(T, Y), u); scalars copied; step counter 0; thermodynamic pressure
  * (pi, q, K) = (1, 0, 0).  Device FP64 inputs; scal may be NULL when S == 0. */

@@ -74,6 +74,7 @@ def _load():
         "lbm_create": [P(LbmParams), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                        P(c_void_p)],
         "lbm_set_geometry": [c_void_p, c_void_p],
+        "lbm_set_wall_distance": [c_void_p, c_void_p],
         "lbm_init_fields": [c_void_p, c_void_p, c_void_p, c_void_p],
         "lbm_step": [c_void_p, c_int32],
         "lbm_fields": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(c_double)],

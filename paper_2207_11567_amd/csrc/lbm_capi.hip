@@ -29,6 +29,7 @@ struct lbm_solver {
   double *stage;
   double *thermo;     // (pi, q, K) of the closed-domain thermodynamic pressure
   bool closed;
+  const double *lvl;  // bound signed wall distance (curved walls) or nullptr
   void *geom;
   std::string err;
 };
@@ -142,6 +143,7 @@ static StepArgs make_args(const lbm_solver *s) {
   a.partials = s->partials;
   a.flag = s->flag;
   a.thermo = s->closed ? s->thermo : nullptr;
+  a.lvl = s->has_geom ? s->lvl : nullptr;
   a.kappa = s->closed ? (p.gamma - 1.0) / p.gamma : 0.0;
   a.nx = p.nx;
   a.ny = p.ny;
@@ -252,6 +254,7 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
   s->stage = (double *)(s->work + L.off_stage);
   s->thermo = (double *)(s->work + L.off_thermo);
   s->closed = p->pth_mode == LBM_PTH_CLOSED;
+  s->lvl = nullptr;
   s->geom = s->work + L.off_geom;
   hipError_t e = hipMemsetAsync(s->work, 0, 256, s->stream);
   if (e == hipSuccess) e = launch_set_thermo(s->thermo, 1.0, 0.0, 0.0, s->stream);
@@ -266,6 +269,7 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
 
 lbm_status lbm_set_geometry(lbm_solver *s, const uint8_t *solid_dev) {
   if (!s) return LBM_E_INVALID;
+  s->lvl = nullptr;
   if (!solid_dev) {
     s->has_geom = false;
     return LBM_OK;
@@ -274,6 +278,22 @@ lbm_status lbm_set_geometry(lbm_solver *s, const uint8_t *solid_dev) {
   hipError_t e = launch_geometry(s->Q, solid_dev, s->geom, s->p.nx, s->p.ny, s->p.nz, s->N, a.face, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "geometry kernel");
   s->has_geom = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_wall_distance(lbm_solver *s, const double *phi_dev) {
+  if (!s) return LBM_E_INVALID;
+  s->lvl = nullptr;
+  if (!phi_dev) {
+    s->has_geom = false;
+    return LBM_OK;
+  }
+  StepArgs a = make_args(s);
+  hipError_t e = launch_geometry_levelset(s->Q, phi_dev, s->geom, s->p.nx, s->p.ny, s->p.nz, s->N, a.face,
+                                          s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "geometry kernel");
+  s->has_geom = true;
+  s->lvl = phi_dev;
   return LBM_OK;
 }
 

@@ -12,16 +12,27 @@ hipError_t launch_d2q9(int prec, int ns, int kind, const StepArgs &a, int nblock
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_geometry(int Q, const uint8_t *solid, void *geom, int nx, int ny, int nz, long long N,
-                           const int *f, hipStream_t st) {
+template <class Src>
+static hipError_t geometry(int Q, const Src *solid, void *geom, int nx, int ny, int nz, long long N, const int *f,
+                           hipStream_t st) {
   const int nb = (int)((N + 255) / 256);
   if (Q == 9)
-    hipLaunchKernelGGL(geometry_kernel<9>, dim3(nb), dim3(256), 0, st, solid, geom, nx, ny, nz, N, f[0], f[1],
-                       f[2], f[3], f[4], f[5]);
+    hipLaunchKernelGGL((geometry_kernel<9, Src>), dim3(nb), dim3(256), 0, st, solid, geom, nx, ny, nz, N, f[0],
+                       f[1], f[2], f[3], f[4], f[5]);
   else
-    hipLaunchKernelGGL(geometry_kernel<27>, dim3(nb), dim3(256), 0, st, solid, geom, nx, ny, nz, N, f[0], f[1],
-                       f[2], f[3], f[4], f[5]);
+    hipLaunchKernelGGL((geometry_kernel<27, Src>), dim3(nb), dim3(256), 0, st, solid, geom, nx, ny, nz, N, f[0],
+                       f[1], f[2], f[3], f[4], f[5]);
   return hipGetLastError();
+}
+
+hipError_t launch_geometry(int Q, const uint8_t *solid, void *geom, int nx, int ny, int nz, long long N,
+                           const int *f, hipStream_t st) {
+  return geometry(Q, solid, geom, nx, ny, nz, N, f, st);
+}
+
+hipError_t launch_geometry_levelset(int Q, const double *phi, void *geom, int nx, int ny, int nz, long long N,
+                                    const int *f, hipStream_t st) {
+  return geometry(Q, phi, geom, nx, ny, nz, N, f, st);
 }
 
 hipError_t launch_finalize(const double *partials, int nblocks, double *stage, double *out, hipStream_t st,

@@ -15,6 +15,8 @@ hipError_t launch_d3q27(int prec, int ns, int kind, const StepArgs &a, int nbloc
                         const double *Ph, const double *u, const double *scal);
 hipError_t launch_geometry(int Q, const uint8_t *solid, void *geom, int nx, int ny, int nz, long long N,
                            const int *face, hipStream_t st);
+hipError_t launch_geometry_levelset(int Q, const double *phi, void *geom, int nx, int ny, int nz, long long N,
+                                    const int *face, hipStream_t st);
 // Adjoint launches (lbm_adjoint.hip).  kind 0: reverse step (p0 lamB, p1 lamT', p2 lamA out,
 // p3 lamT out, p4 coefficient scratch); 1/2: objective sums / gradient (p2 lamA, p3 lamT);
 // 3: reverse of the initialisation (p0 lamA, p1 lamT, u0, gu out, p3 grad T out).

@@ -13,6 +13,9 @@
 // density, its rate q = dln(pi)/dt adds the pressure work kappa T q to the temperature
 // right-hand side and shifts Lambda to the velocity divergence Lambda - q, and the
 // finalisation of the sums sets pi for the next step from the mass the domain holds.
+// With a signed wall distance bound (curved walls), links from solid cells use the
+// linearly interpolated bounce-back and scalar stencil points in solid cells take the
+// value at their mirror image about the wall (boundary cells only).
 #pragma once
 
 #include <type_traits>
@@ -41,6 +44,7 @@ struct StepArgs {
   int *flag;           // bit 0: non-finite value seen
   const double *thermo;  // closed domain: device (pi, q, K); nullptr when P_th is constant
   double kappa;        // (gamma - 1)/gamma
+  const double *lvl;   // signed wall distance per node (curved walls) or nullptr
   double *f_P, *f_rho, *f_u, *f_scal;   // field outputs (extract mode)
   int nx, ny, nz;
   long long N;
@@ -69,6 +73,7 @@ template <class R> struct KArgs {
   double *partials;
   int *flag;
   const double *thermo;
+  const double *lvl;
   double *f_P, *f_rho, *f_u, *f_scal;
   int nx, ny, nz, N;
   int face[6];
@@ -86,7 +91,7 @@ template <class R> struct KArgs {
 template <class R> KArgs<R> to_kargs(const StepArgs &a) {
   KArgs<R> k;
   k.pop_in = a.pop_in; k.pop_out = a.pop_out; k.scal_in = a.scal_in; k.scal_out = a.scal_out;
-  k.geom = a.geom; k.partials = a.partials; k.flag = a.flag; k.thermo = a.thermo;
+  k.geom = a.geom; k.partials = a.partials; k.flag = a.flag; k.thermo = a.thermo; k.lvl = a.lvl;
   k.kap = (R)a.kappa;
   k.f_P = a.f_P; k.f_rho = a.f_rho; k.f_u = a.f_u; k.f_scal = a.f_scal;
   k.nx = a.nx; k.ny = a.ny; k.nz = a.nz; k.N = (int)a.N;
@@ -185,6 +190,14 @@ template <class T> __device__ __forceinline__ T ldg_nt(const T *base, unsigned i
 template <class T> __device__ __forceinline__ void stg_nt(T *base, unsigned idx, T v) {
   __builtin_nontemporal_store(v, (T *)((char *)base + idx * (unsigned)sizeof(T)));
 }
+
+// (1 - p) a + p b, exact at p = 0 and p = 1.
+template <class R> __device__ __forceinline__ R lerp(R a, R b, R p) { return (R(1) - p) * a + p * b; }
+
+// Interpolation weight toward the second node for a mirror image at distance p <= 1 from
+// the first fluid node: p itself, or, for an image between the wall and that node
+// (p < 0), the even quadratic through the two nodes (zero gradient at the wall).
+template <class R> __device__ __forceinline__ R image_weight(R p) { return p >= R(0) ? p : fdiv(p, R(2) - p); }
 
 
 // Block reduction of NSUM doubles into partials[tile*NSUM ..] in a fixed order: every
@@ -393,7 +406,27 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           const bool solid_src = (gw >> i) & 1;
           const int io = Q - 1 - i;
           if (wall || (!inl && !outl && solid_src)) {
-            gh[i] = decode<R>(ldg(pin + (size_t)io * N, un));
+            const R gopp = decode<R>(ldg(pin + (size_t)io * N, un));
+            gh[i] = gopp;
+            if (!wall && a.lvl) {
+              // interpolated bounce-back, the wall at the fraction q of the link to r - c_i
+              const unsigned ms = un + (unsigned)(off[0][2 - c[0]] + off[1][2 - c[1]] + (D == 3 ? off[2][2 - c[2]] : 0));
+              const double l0 = a.lvl[n];
+              const R qf = (R)(l0 / (l0 - a.lvl[ms]));
+              if (qf < R(0.5)) {
+                bool ahead_fluid = !((gw >> io) & 1);        // r + c_i is a fluid node
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                  if (c[d] != 0 && code[d][2 + c[d]] >= 0) ahead_fluid = false;
+                if (ahead_fluid) {
+                  const unsigned ma = un + (unsigned)(off[0][2 + c[0]] + off[1][2 + c[1]] + (D == 3 ? off[2][2 + c[2]] : 0));
+                  gh[i] = lerp(decode<R>(ldg(pin + (size_t)io * N, ma)), gopp, R(2) * qf);
+                }
+              } else {
+                const R h = fdiv(R(1), R(2) * qf);
+                gh[i] = gopp * h + (R(1) - h) * decode<R>(ldg(pin + (size_t)i * N, un));
+              }
+            }
           } else if (inl) {
             const R cu = R(c[0]) * uw_in[0] + R(c[1]) * uw_in[1] + R(c[2]) * uw_in[2];
             gh[i] = decode<R>(ldg(pin + (size_t)io * N, un)) + R(2.0 * wgt<Q>(i)) * rho_in * cu * invP0;
@@ -460,10 +493,50 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
                 vm1[q] = sm1 == ST_FLUID ? (R)ldg(sq, mm1) : sm1 == ST_INLET ? phin[q] : phi0[q];
               }
             }
+            // curved walls: mirror images of solid cells at -1 / +1 (c1), of the stencil
+            // points at -2 / +2 behind them (c2, image at p2 from the cell) and of a solid
+            // cell at -2 / +2 behind a fluid neighbour (c3, weight w3 from that neighbour)
+            bool c1m = false, c1p = false, c2m = false, c2p = false, c3m = false, c3p = false;
+            R w1m = R(0), w1p = R(0), p2m = R(0), p2p = R(0), w3m = R(0), w3p = R(0);
+            if (!FAST && a.lvl) {
+              const double l0 = a.lvl[n];
+              if (sm1 == ST_SOLID && code[d][1] < 0 && sp1 == ST_FLUID) {
+                const R qw = (R)(l0 / (l0 - a.lvl[mm1]));
+                c1m = true;
+                w1m = image_weight(R(1) - R(2) * qw);
+                p2m = R(2) - R(2) * qw;
+                c2m = p2m <= R(1) || sp2 == ST_FLUID;
+              } else if (sm1 == ST_FLUID && sm2 == ST_SOLID && code[d][0] < 0) {
+                const double l1 = a.lvl[mm1];
+                c3m = true;
+                w3m = image_weight(R(1) - R(2) * (R)(l1 / (l1 - a.lvl[mm2])));
+              }
+              if (sp1 == ST_SOLID && code[d][3] < 0 && sm1 == ST_FLUID) {
+                const R qw = (R)(l0 / (l0 - a.lvl[mp1]));
+                c1p = true;
+                w1p = image_weight(R(1) - R(2) * qw);
+                p2p = R(2) - R(2) * qw;
+                c2p = p2p <= R(1) || sm2 == ST_FLUID;
+              } else if (sp1 == ST_FLUID && sp2 == ST_SOLID && code[d][4] < 0) {
+                const double l1 = a.lvl[mp1];
+                c3p = true;
+                w3p = image_weight(R(1) - R(2) * (R)(l1 / (l1 - a.lvl[mp2])));
+              }
+#pragma unroll
+              for (int q = 0; q < NS; ++q) {
+                const R am = vm1[q], ap = vp1[q];
+                if (c1m) vm1[q] = lerp(phi0[q], ap, w1m);
+                if (c1p) vp1[q] = lerp(phi0[q], am, w1p);
+              }
+            }
             // density at +-1 and diffusion through the two faces
             R rp = rho0, rm = rho0;
-            if (FAST || sp1 == ST_FLUID) rp = density<NS, R>(a.th, vp1, pim); else if (sp1 == ST_INLET) rp = rho_in;
-            if (FAST || sm1 == ST_FLUID) rm = density<NS, R>(a.th, vm1, pim); else if (sm1 == ST_INLET) rm = rho_in;
+            if (FAST || sp1 == ST_FLUID) rp = density<NS, R>(a.th, vp1, pim);
+            else if (sp1 == ST_INLET) rp = rho_in;
+            else if (c1p) rp = density<NS, R>(a.th, vp1, pim);
+            if (FAST || sm1 == ST_FLUID) rm = density<NS, R>(a.th, vm1, pim);
+            else if (sm1 == ST_INLET) rm = rho_in;
+            else if (c1m) rm = density<NS, R>(a.th, vm1, pim);
             gradrho[d] = R(0.5) * (rp - rm);
             // face coefficients: arithmetic mean of rho D (uniform when rho nu is constant)
             R cfp, cfm;
@@ -496,6 +569,10 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
                   else vm2 = sm1 == ST_SOLID ? vp1[q] : sm1 == ST_INLET ? phin[q] : v0;
                   if (sp1 == ST_FLUID) vp2 = sp2 == ST_FLUID ? (R)ldg(sq, mp2) : sp2 == ST_INLET ? phin[q] : vp1[q];
                   else vp2 = sp1 == ST_SOLID ? vm1[q] : sp1 == ST_INLET ? phin[q] : v0;
+                  if (c2m) vm2 = p2m <= R(1) ? lerp(v0, vp1[q], p2m) : lerp(vp1[q], (R)ldg(sq, mp2), p2m - R(1));
+                  else if (c3m) vm2 = lerp(vm1[q], v0, w3m);
+                  if (c2p) vp2 = p2p <= R(1) ? lerp(v0, vm1[q], p2p) : lerp(vm1[q], (R)ldg(sq, mm2), p2p - R(1));
+                  else if (c3p) vp2 = lerp(vp1[q], v0, w3p);
                   vU2 = up ? vm2 : vp2;
                 }
                 const R vU1 = up ? vm1[q] : vp1[q];
@@ -717,9 +794,12 @@ static __global__ void set_thermo_kernel(double *thermo, double pi, double q, do
   }
 }
 
-// Geometry words from a solid mask (see GeomWord).
-template <int Q>
-__global__ __launch_bounds__(256) void geometry_kernel(const uint8_t *solid, void *geom, int nx, int ny,
+__device__ __forceinline__ bool solid_at(const uint8_t *s, long long m) { return s[m] != 0; }
+__device__ __forceinline__ bool solid_at(const double *phi, long long m) { return phi[m] < 0.0; }
+
+// Geometry words from a solid mask, or from a signed wall distance (solid where < 0).
+template <int Q, class Src>
+__global__ __launch_bounds__(256) void geometry_kernel(const Src *solid, void *geom, int nx, int ny,
                                                         int nz, long long N, int f0, int f1, int f2,
                                                         int f3, int f4, int f5) {
   using GW = typename GeomWord<Q>::T;
@@ -733,13 +813,13 @@ __global__ __launch_bounds__(256) void geometry_kernel(const uint8_t *solid, voi
     return (long long)X + (long long)nx * ((long long)Y + (long long)ny * Z);
   };
   GW w = 0;
-  if (solid[n]) w |= GW(1) << bit_self<Q>();
+  if (solid_at(solid, n)) w |= GW(1) << bit_self<Q>();
   for (int i = 0; i < Q; ++i) {
     const int c[3] = {cx(i), cy(i), D == 3 ? cz(i) : 0};
     bool out = ax.code[2 - c[0]] >= 0 || ay.code[2 - c[1]] >= 0 || (D == 3 && az.code[2 - c[2]] >= 0);
     if (out || i == (Q - 1) / 2) continue;
     const long long m = lin(ax.idx[2 - c[0]], ay.idx[2 - c[1]], D == 3 ? az.idx[2 - c[2]] : z);
-    if (solid[m]) w |= GW(1) << i;
+    if (solid_at(solid, m)) w |= GW(1) << i;
   }
   for (int d = 0; d < D; ++d) {
     const AxisNb &A = d == 0 ? ax : d == 1 ? ay : az;
@@ -747,7 +827,7 @@ __global__ __launch_bounds__(256) void geometry_kernel(const uint8_t *solid, voi
       const int k = neg ? 0 : 4;   // position -2 or +2
       if (A.code[k] >= 0) continue;
       const long long m = d == 0 ? lin(A.idx[k], y, z) : d == 1 ? lin(x, A.idx[k], z) : lin(x, y, A.idx[k]);
-      if (solid[m]) w |= GW(1) << bit_far<Q>(d, neg);
+      if (solid_at(solid, m)) w |= GW(1) << bit_far<Q>(d, neg);
     }
   }
   ((GW *)geom)[n] = w;

@@ -77,6 +77,16 @@ class Solver:
         self._mask = self._dev(solid, torch.uint8).reshape(self.shape)
         self._chk(C.lib().lbm_set_geometry(self._h, _ptr(self._mask)))
 
+    def set_wall_distance(self, phi):
+        """Curved walls from the signed wall distance at the nodes (solid where < 0); the
+        device copy is kept alive by the solver while bound."""
+        if phi is None:
+            self._phi = None
+            self._chk(C.lib().lbm_set_wall_distance(self._h, None))
+            return
+        self._phi = self._dev(phi, torch.float64).reshape(self.shape).contiguous()
+        self._chk(C.lib().lbm_set_wall_distance(self._h, _ptr(self._phi)))
+
     def init_fields(self, P_h, u, scal=None):
         P = self._dev(P_h).reshape(self.shape)
         U = self._dev(u).reshape((self.D,) + self.shape)
