@@ -32,10 +32,14 @@ template <int Q, int PREC, int NS>
 hipError_t launch_one(int kind, const StepArgs &a, int nblocks, hipStream_t st, const double *Ph,
                       const double *u, const double *scal) {
   using R = typename Prec<PREC>::R;
-  if (kind == LAUNCH_STEP)
-    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
+  if (kind == LAUNCH_STEP && a.lvl)
+    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, true>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
+  else if (kind == LAUNCH_STEP)
+    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, false>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
+  else if (kind == LAUNCH_EXTRACT && a.lvl)
+    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, true>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
   else if (kind == LAUNCH_EXTRACT)
-    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
+    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, false>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
   else
     hipLaunchKernelGGL((init_kernel<Q, PREC, NS>), dim3(nblocks), dim3(256), 0, st, to_kargs<double>(a), Ph,
                        u, scal);

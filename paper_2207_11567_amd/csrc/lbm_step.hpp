@@ -240,7 +240,9 @@ __device__ __forceinline__ double w_over_T(const ThermoT<R> &t, const R (&v)[NS 
   }
 }
 
-template <int Q, int PREC, int NS, bool EXTRACT>
+// CURVED: a signed wall distance is bound (a.lvl); compiled separately so that the
+// staircase instances carry none of the curved-wall code.
+template <int Q, int PREC, int NS, bool EXTRACT, bool CURVED>
 __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R> a) {
   using P = Prec<PREC>;
   using St = typename P::St;
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           if (wall || (!inl && !outl && solid_src)) {
             const R gopp = decode<R>(ldg(pin + (size_t)io * N, un));
             gh[i] = gopp;
-            if (!wall && a.lvl) {
+            if (CURVED && !wall) {
               // interpolated bounce-back, the wall at the fraction q of the link to r - c_i
               const unsigned ms = un + (unsigned)(off[0][2 - c[0]] + off[1][2 - c[1]] + (D == 3 ? off[2][2 - c[2]] : 0));
               const double l0 = a.lvl[n];
@@ -498,7 +500,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             // cell at -2 / +2 behind a fluid neighbour (c3, weight w3 from that neighbour)
             bool c1m = false, c1p = false, c2m = false, c2p = false, c3m = false, c3p = false;
             R w1m = R(0), w1p = R(0), p2m = R(0), p2p = R(0), w3m = R(0), w3p = R(0);
-            if (!FAST && a.lvl) {
+            if (CURVED && !FAST) {
               const double l0 = a.lvl[n];
               if (sm1 == ST_SOLID && code[d][1] < 0 && sp1 == ST_FLUID) {
                 const R qw = (R)(l0 / (l0 - a.lvl[mm1]));
