@@ -85,7 +85,7 @@ def bytes_per_cell(p):
     return 2 * Q * sp + 2 * NS * ss + 64.0 / 256.0
 
 
-def run_gpu(name, steps, warmup, precision=None):
+def run_gpu(name, steps, warmup, precision=None, observables=False):
     import torch
 
     from paper_2207_11567_amd import Solver
@@ -97,6 +97,12 @@ def run_gpu(name, steps, warmup, precision=None):
                        torch.from_numpy(s) if s is not None else None)
     del P, u, s
     N = p["nx"] * p["ny"] * p["nz"]
+    extra = {}
+    if observables:
+        # running statistics at every level and 8 probes along the mid-line
+        solver.set_statistics(1)
+        cells = [int(p["nx"] * (k + 1) / 9) + p["nx"] * (p["ny"] // 2) for k in range(8)]
+        solver.set_probes(cells, capacity=steps + warmup)
     solver.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -107,6 +113,16 @@ def run_gpu(name, steps, warmup, precision=None):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     sums = solver.step_sums()            # raises on a non-finite value
+    if p["physics"] in ("one_step", "two_step"):
+        T_u, T_b = (p["chem"][2], p["chem"][3]) if p["physics"] == "one_step" else (p["inlet_T"], 1950.0)
+        solver.flame_surface(T_u, T_b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            extra["flame_surface"] = solver.flame_surface(T_u, T_b)
+        extra["flame_surface_ms"] = (time.perf_counter() - t0) / 20 * 1e3
+    if p.get("pth_mode") == "closed":
+        extra["pth_ratio"] = solver.thermo_pressure()[0]
     bpc = bytes_per_cell(p) + (4 if (solid is not None and p["lattice"] == "D2Q9") else 0) \
         + (8 if (solid is not None and p["lattice"] == "D3Q27") else 0)
     t_launch = ms / 1e3 / steps
@@ -116,7 +132,7 @@ def run_gpu(name, steps, warmup, precision=None):
     torch.cuda.empty_cache()
     return {"workload": name, "desc": desc, "params": p, "cells": N, "steps": steps,
             "ms_per_step": ms / steps, "mlups": N * steps / (ms / 1e3) / 1e6,
-            "bytes_per_cell": bpc, "achieved_gbs": achieved, "sums": sums}
+            "bytes_per_cell": bpc, "achieved_gbs": achieved, "sums": sums, "observables": extra}
 
 
 def cpu_baseline(name, budget_s=15.0):
@@ -272,6 +288,8 @@ def main():
                     choices=["reacting_box", "flame2d", "hit", "tgv", "passive_box", "chamber2d",
                              "chamber2d_open"])
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "fp16s"])
+    ap.add_argument("--observables", action="store_true",
+                    help="sample running statistics and 8 probes at every step of the main workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
@@ -300,7 +318,7 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    main_res = run_gpu(args.workload, args.steps, args.warmup, args.precision)
+    main_res = run_gpu(args.workload, args.steps, args.warmup, args.precision, args.observables)
     p = main_res["params"]
     N = main_res["cells"]
     print(f"# {args.workload}: {main_res['mlups']:.1f} MLUPS, {main_res['ms_per_step']:.3f} ms/step",
@@ -317,13 +335,17 @@ def main():
         for name, prec, k in (("tgv", "fp64", 1000), ("flame2d", "fp64", 400),
                               ("flame2d", "fp32", 400), ("hit", "fp64", 40), ("hit", "fp32", 60),
                               ("hit", "fp16s", 60), ("passive_box", "fp32", 100),
-                              ("chamber2d", "fp64", 400), ("chamber2d_open", "fp64", 400)):
-            r = run_gpu(name, k, 10, prec)
+                              ("chamber2d", "fp64", 400), ("chamber2d_open", "fp64", 400),
+                              ("chamber2d+observables", "fp64", 400)):
+            obs = name.endswith("+observables")
+            r = run_gpu(name.split("+")[0], k, 10, prec, observables=obs)
             extra[f"{name}_{prec}"] = {"mlups": round(r["mlups"], 1),
                                        "ms_per_step": round(r["ms_per_step"], 4),
                                        "achieved_gbs": round(r["achieved_gbs"], 1),
                                        "hbm_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
                                        "cells": r["cells"], "desc": r["desc"]}
+            if r["observables"]:
+                extra[f"{name}_{prec}"]["observables"] = {k2: round(v, 6) for k2, v in r["observables"].items()}
             print(f"# {name} {prec}: {r['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
         extra["precision_error_vs_fp64"] = precision_errors()
         extra["differentiation"] = differentiation()

@@ -170,6 +170,33 @@ lbm_status lbm_get_state(lbm_solver *s, void *pops_dst, void *scal_dst, int64_t 
 lbm_status lbm_set_state(lbm_solver *s, const void *pops_src, const void *scal_src,
                          int64_t step);
 
+/* ------------------------------------------------------------------ observables (Sec. 3)
+ * Running statistics (Sec. 3.2: time-averaged velocity components, their RMS and the RMS of
+ * the pressure fluctuations).  acc_dev: caller buffer of 2 (D+1) N FP64 values, zeroed
+ * here; every lbm_step level n with n % every == 0 (the state before that step) is sampled
+ * into running means and sums of squared deviations (Welford) of u_d and P_h.  NULL stops
+ * sampling.  every < 1 with a buffer: LBM_E_INVALID. */
+lbm_status lbm_set_statistics(lbm_solver *s, double *acc_dev, int32_t every);
+
+/* Mean [D+1][N] (u_x, u_y, [u_z,] P_h) and RMS (population standard deviation) fields of
+ * the samples so far, FP64 device outputs (either may be NULL), and the sample count.
+ * LBM_E_STATE without samples.  Synchronises. */
+lbm_status lbm_statistics(lbm_solver *s, double *mean_dev, double *rms_dev, int64_t *samples);
+
+/* Probes (Sec. 3.2: velocity and pressure recorded at every step at points of the burner
+ * axis, for their spectra): up to 8 cell indices (host array); record_dev receives one row
+ * [nprobe][D+1] = (u..., P_h) per stepped level, until `capacity` rows.  NULL record or
+ * nprobe 0 stops recording.  Out-of-range cells, nprobe > 8: LBM_E_INVALID. */
+lbm_status lbm_set_probes(lbm_solver *s, const int64_t *cells_host, int32_t nprobe, double *record_dev,
+                          int64_t capacity);
+lbm_status lbm_probe_rows(lbm_solver *s, int64_t *rows);
+
+/* Generalised flame surface (Sec. 3.1: flame-surface evolution in the chamber): the sum over
+ * fluid cells of |grad c|, c = (T - T_u)/(T_b - T_u), central differences with the ghost
+ * rules of grad rho, in lattice units (area in 3-D, length in 2-D), at the current level.
+ * Needs a temperature (S >= 1).  Synchronises. */
+lbm_status lbm_flame_surface(lbm_solver *s, double T_u, double T_b, double *surface_host);
+
 /* Thermodynamic pressure state of the current level, three FP64 values on the host:
  * pi = P_th/P_th(0), q = dln(pi)/dt of this level (per time step), K = the held
  * mass constant (0 until the first step of a closed domain fixes it).  Open domains keep

@@ -30,6 +30,13 @@ struct lbm_solver {
   double *thermo;     // (pi, q, K) of the closed-domain thermodynamic pressure
   bool closed;
   const double *lvl;  // bound signed wall distance (curved walls) or nullptr
+  double *stats;      // running statistics buffer or nullptr
+  int stats_every;
+  long long stats_k;  // samples taken
+  double *probe_rec;  // probe record or nullptr
+  int nprobe;
+  int probe[8];
+  long long probe_cap, probe_rows;
   void *geom;
   std::string err;
 };
@@ -255,6 +262,12 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
   s->thermo = (double *)(s->work + L.off_thermo);
   s->closed = p->pth_mode == LBM_PTH_CLOSED;
   s->lvl = nullptr;
+  s->stats = nullptr;
+  s->stats_every = 1;
+  s->stats_k = 0;
+  s->probe_rec = nullptr;
+  s->nprobe = 0;
+  s->probe_cap = s->probe_rows = 0;
   s->geom = s->work + L.off_geom;
   hipError_t e = hipMemsetAsync(s->work, 0, 256, s->stream);
   if (e == hipSuccess) e = launch_set_thermo(s->thermo, 1.0, 0.0, 0.0, s->stream);
@@ -334,6 +347,19 @@ lbm_status lbm_step(lbm_solver *s, int32_t nsteps) {
     a.scal_in = s->scal[s->cur];
     a.scal_out = s->scal[1 - s->cur];
     a.step = s->step;
+    a.stats = nullptr;
+    if (s->stats && s->step % s->stats_every == 0) {
+      s->stats_k += 1;
+      a.stats = s->stats;
+      a.inv_k = 1.0 / (double)s->stats_k;
+    }
+    a.probe_out = nullptr;
+    if (s->probe_rec && s->probe_rows < s->probe_cap) {
+      a.probe_out = s->probe_rec + (size_t)s->probe_rows * s->nprobe * (s->D + 1);
+      a.nprobe = s->nprobe;
+      for (int j = 0; j < 8; ++j) a.probe[j] = s->probe[j];
+      s->probe_rows += 1;
+    }
     hipError_t e = launch(s, LAUNCH_STEP, a);
     if (e != hipSuccess) return hip_fail(s, e, "step kernel");
     if (s->closed) {
@@ -424,6 +450,87 @@ lbm_status lbm_set_state(lbm_solver *s, const void *pops_src, const void *scal_s
   if (e != hipSuccess) return hip_fail(s, e, "copying the state in");
   s->step = step;
   s->initialized = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_statistics(lbm_solver *s, double *acc_dev, int32_t every) {
+  if (!s) return LBM_E_INVALID;
+  if (acc_dev && every < 1) {
+    s->err = "statistics: every must be >= 1";
+    return LBM_E_INVALID;
+  }
+  s->stats = acc_dev;
+  s->stats_every = acc_dev ? every : 1;
+  s->stats_k = 0;
+  if (acc_dev) {
+    hipError_t e = hipMemsetAsync(acc_dev, 0, (size_t)2 * (s->D + 1) * s->N * sizeof(double), s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "clearing the statistics");
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_statistics(lbm_solver *s, double *mean_dev, double *rms_dev, int64_t *samples) {
+  if (!s) return LBM_E_INVALID;
+  if (!s->stats || s->stats_k == 0) {
+    s->err = "statistics: no samples (bind a buffer with lbm_set_statistics, then step)";
+    return LBM_E_STATE;
+  }
+  hipError_t e = launch_statistics(s->stats, s->D, s->N, s->stats_k, s->p.rho_ref / 3.0, mean_dev, rms_dev, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "statistics kernel");
+  if (samples) *samples = s->stats_k;
+  return check_flag(s);
+}
+
+lbm_status lbm_set_probes(lbm_solver *s, const int64_t *cells_host, int32_t nprobe, double *record_dev,
+                          int64_t capacity) {
+  if (!s) return LBM_E_INVALID;
+  if (!record_dev || nprobe == 0) {
+    s->probe_rec = nullptr;
+    s->nprobe = 0;
+    s->probe_cap = s->probe_rows = 0;
+    return LBM_OK;
+  }
+  if (nprobe < 0 || nprobe > 8 || !cells_host || capacity < 1) {
+    s->err = "probes: 1..8 cells, a record buffer and capacity >= 1 required";
+    return LBM_E_INVALID;
+  }
+  for (int j = 0; j < nprobe; ++j)
+    if (cells_host[j] < 0 || cells_host[j] >= s->N) {
+      s->err = "probes: cell index out of range";
+      return LBM_E_INVALID;
+    }
+  for (int j = 0; j < 8; ++j) s->probe[j] = j < nprobe ? (int)cells_host[j] : -1;
+  s->nprobe = nprobe;
+  s->probe_rec = record_dev;
+  s->probe_cap = capacity;
+  s->probe_rows = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_probe_rows(lbm_solver *s, int64_t *rows) {
+  if (!s || !rows) return LBM_E_INVALID;
+  *rows = s->probe_rows;
+  return LBM_OK;
+}
+
+lbm_status lbm_flame_surface(lbm_solver *s, double T_u, double T_b, double *surface_host) {
+  if (!s || !surface_host) return LBM_E_INVALID;
+  if (s->NS < 1 || !(T_b != T_u)) {
+    s->err = "flame surface: needs a temperature and T_b != T_u";
+    return LBM_E_INVALID;
+  }
+  if (!s->initialized) {
+    s->err = "flame surface before initialisation";
+    return LBM_E_STATE;
+  }
+  StepArgs a = make_args(s);
+  a.scal_in = s->scal[s->cur];
+  hipError_t e = launch_surface(s->Q, s->prec, a, s->nblocks, s->stream, T_u, T_b);
+  if (e == hipSuccess) e = launch_finalize(s->partials, s->nblocks, s->stage, s->sums, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(surface_host, s->sums, sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "flame surface");
   return LBM_OK;
 }
 

@@ -44,6 +44,26 @@ hipError_t launch_finalize(const double *partials, int nblocks, double *stage, d
   return hipGetLastError();
 }
 
+hipError_t launch_surface(int Q, int prec, const StepArgs &a, int nblocks, hipStream_t st, double T_u, double T_b) {
+  const KArgs<double> k = to_kargs<double>(a);
+  const double inv = 1.0 / (T_b - T_u);
+  if (Q == 9) {
+    if (prec == 0) hipLaunchKernelGGL((surface_kernel<9, 0>), dim3(nblocks), dim3(256), 0, st, k, T_u, inv);
+    else hipLaunchKernelGGL((surface_kernel<9, 1>), dim3(nblocks), dim3(256), 0, st, k, T_u, inv);
+  } else {
+    if (prec == 0) hipLaunchKernelGGL((surface_kernel<27, 0>), dim3(nblocks), dim3(256), 0, st, k, T_u, inv);
+    else hipLaunchKernelGGL((surface_kernel<27, 1>), dim3(nblocks), dim3(256), 0, st, k, T_u, inv);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_statistics(const double *acc, int D, long long N, long long k, double P0, double *mean, double *rms,
+                             hipStream_t st) {
+  const int nb = (int)((N + 255) / 256);
+  hipLaunchKernelGGL(statistics_kernel, dim3(nb), dim3(256), 0, st, acc, D, N, (double)k, P0, mean, rms);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_thermo(double *thermo, double pi, double q, double K, hipStream_t st) {
   hipLaunchKernelGGL(set_thermo_kernel, dim3(1), dim3(64), 0, st, thermo, pi, q, K);
   return hipGetLastError();

@@ -27,16 +27,21 @@ hipError_t launch_adjoint(int prec, int ns, int kind, const StepArgs &sa, int nb
 hipError_t launch_finalize(const double *partials, int nblocks, double *stage, double *out, hipStream_t st,
                            double *thermo = nullptr);
 hipError_t launch_set_thermo(double *thermo, double pi, double q, double K, hipStream_t st);
+// Observables: flame-surface block records (slot 0 of the partials) and mean / RMS fields.
+hipError_t launch_surface(int Q, int prec, const StepArgs &a, int nblocks, hipStream_t st, double T_u, double T_b);
+hipError_t launch_statistics(const double *acc, int D, long long N, long long k, double P0, double *mean, double *rms,
+                             hipStream_t st);
 
 template <int Q, int PREC, int NS>
 hipError_t launch_one(int kind, const StepArgs &a, int nblocks, hipStream_t st, const double *Ph,
                       const double *u, const double *scal) {
   using R = typename Prec<PREC>::R;
-  if (kind == LAUNCH_STEP && a.lvl)
+  const bool full = a.lvl || a.stats || a.probe_out;
+  if (kind == LAUNCH_STEP && full)
     hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, true>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
   else if (kind == LAUNCH_STEP)
     hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, false>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
-  else if (kind == LAUNCH_EXTRACT && a.lvl)
+  else if (kind == LAUNCH_EXTRACT && full)
     hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, true>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
   else if (kind == LAUNCH_EXTRACT)
     hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, false>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));

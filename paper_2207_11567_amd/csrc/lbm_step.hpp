@@ -45,6 +45,12 @@ struct StepArgs {
   const double *thermo;  // closed domain: device (pi, q, K); nullptr when P_th is constant
   double kappa;        // (gamma - 1)/gamma
   const double *lvl;   // signed wall distance per node (curved walls) or nullptr
+  double *stats;       // running statistics [2(D+1)][N] (means, then sums of squared
+                       // deviations) of u_d and P_h - P0, or nullptr when not sampled
+  double inv_k;        // 1/k for the k-th sample
+  double *probe_out;   // row of this level in the probe record ([nprobe][D+1]) or nullptr
+  int nprobe;
+  int probe[8];        // probe cells
   double *f_P, *f_rho, *f_u, *f_scal;   // field outputs (extract mode)
   int nx, ny, nz;
   long long N;
@@ -74,6 +80,11 @@ template <class R> struct KArgs {
   int *flag;
   const double *thermo;
   const double *lvl;
+  double *stats;
+  double inv_k;
+  double *probe_out;
+  int nprobe;
+  int probe[8];
   double *f_P, *f_rho, *f_u, *f_scal;
   int nx, ny, nz, N;
   int face[6];
@@ -92,6 +103,8 @@ template <class R> KArgs<R> to_kargs(const StepArgs &a) {
   KArgs<R> k;
   k.pop_in = a.pop_in; k.pop_out = a.pop_out; k.scal_in = a.scal_in; k.scal_out = a.scal_out;
   k.geom = a.geom; k.partials = a.partials; k.flag = a.flag; k.thermo = a.thermo; k.lvl = a.lvl;
+  k.stats = a.stats; k.inv_k = a.inv_k; k.probe_out = a.probe_out; k.nprobe = a.nprobe;
+  for (int j = 0; j < 8; ++j) k.probe[j] = a.probe[j];
   k.kap = (R)a.kappa;
   k.f_P = a.f_P; k.f_rho = a.f_rho; k.f_u = a.f_u; k.f_scal = a.f_scal;
   k.nx = a.nx; k.ny = a.ny; k.nz = a.nz; k.N = (int)a.N;
@@ -240,9 +253,10 @@ __device__ __forceinline__ double w_over_T(const ThermoT<R> &t, const R (&v)[NS 
   }
 }
 
-// CURVED: a signed wall distance is bound (a.lvl); compiled separately so that the
-// staircase instances carry none of the curved-wall code.
-template <int Q, int PREC, int NS, bool EXTRACT, bool CURVED>
+// FULL: the instance that also carries curved walls (a.lvl) and the observables
+// (a.stats, a.probe_out), each switched on by its pointer; the plain instances carry none
+// of that code, so their register allocation is that of the bare step.
+template <int Q, int PREC, int NS, bool EXTRACT, bool FULL>
 __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R> a) {
   using P = Prec<PREC>;
   using St = typename P::St;
@@ -410,7 +424,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           if (wall || (!inl && !outl && solid_src)) {
             const R gopp = decode<R>(ldg(pin + (size_t)io * N, un));
             gh[i] = gopp;
-            if (CURVED && !wall) {
+            if (FULL && !wall && a.lvl) {
               // interpolated bounce-back, the wall at the fraction q of the link to r - c_i
               const unsigned ms = un + (unsigned)(off[0][2 - c[0]] + off[1][2 - c[1]] + (D == 3 ? off[2][2 - c[2]] : 0));
               const double l0 = a.lvl[n];
@@ -500,7 +514,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             // cell at -2 / +2 behind a fluid neighbour (c3, weight w3 from that neighbour)
             bool c1m = false, c1p = false, c2m = false, c2p = false, c3m = false, c3p = false;
             R w1m = R(0), w1p = R(0), p2m = R(0), p2p = R(0), w3m = R(0), w3p = R(0);
-            if (CURVED && !FAST) {
+            if (FULL && !FAST && a.lvl) {
               const double l0 = a.lvl[n];
               if (sm1 == ST_SOLID && code[d][1] < 0 && sp1 == ST_FLUID) {
                 const R qw = (R)(l0 / (l0 - a.lvl[mm1]));
@@ -646,6 +660,29 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
 #pragma unroll
           for (int k = 0; k < NS; ++k) a.f_scal[k * N + n] = (double)phi0[k];
       } else {
+        // ------------------------------------------------------------ observables
+        // running mean and squared-deviation sums (Welford) of u and P_h - P0 at sampled
+        // levels; probe rows (u, P_h) at the probe cells
+        if (FULL && a.stats) {
+          const double x[4] = {(double)u[0], (double)u[1], (double)u[2], (double)Ph - (double)a.P0};
+#pragma unroll
+          for (int j = 0; j <= D; ++j) {
+            const double xv = x[j == D ? 3 : j];
+            double *mp = a.stats + (size_t)j * N + n, *sp = a.stats + (size_t)(D + 1 + j) * N + n;
+            const double m0 = *mp;
+            const double m1 = m0 + (xv - m0) * a.inv_k;
+            *mp = m1;
+            *sp += (xv - m0) * (xv - m1);
+          }
+        }
+        if (FULL && a.probe_out) {
+          for (int j = 0; j < a.nprobe; ++j)
+            if (n == a.probe[j]) {
+#pragma unroll
+              for (int d = 0; d < D; ++d) a.probe_out[j * (D + 1) + d] = (double)u[d];
+              a.probe_out[j * (D + 1) + D] = (double)Ph;
+            }
+        }
         // ------------------------------------------------------------ scalar update
         bool bad = false;
         R phi1[NSV];
@@ -793,6 +830,61 @@ static __global__ void set_thermo_kernel(double *thermo, double pi, double q, do
     thermo[0] = pi;
     thermo[1] = q;
     thermo[2] = K;
+  }
+}
+
+// Generalised flame surface: |grad c| summed over fluid cells, c = (T - T_u)/(T_b - T_u),
+// central differences with the ghost rules of grad rho (own value across walls, solids
+// and the outlet, the inlet temperature across the inlet); FP64 block records.
+template <int Q, int PREC>
+__global__ __launch_bounds__(256) void surface_kernel(KArgs<double> a, double T_u, double inv_dT) {
+  using Sc = typename Prec<PREC>::Sc;
+  using GW = typename GeomWord<Q>::T;
+  constexpr int D = Lat<Q>::D;
+  const int n = blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
+  double red[NSUM];
+#pragma unroll
+  for (int k = 0; k < NSUM; ++k) red[k] = 0.0;
+  if (n < a.N) {
+    const GW gw = a.geom ? ((const GW *)a.geom)[n] : GW(0);
+    if (!(gw & (GW(1) << bit_self<Q>()))) {
+      const Sc *T = (const Sc *)a.scal_in;
+      const int nxy = a.nx * a.ny, z = n / nxy, rem = n - z * nxy, y = rem / a.nx, x = rem - y * a.nx;
+      const int cc[3] = {x, y, z}, ext[3] = {a.nx, a.ny, a.nz};
+      const double t0 = (double)T[n];
+      double g2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const AxisNb ax = axis_nb(cc[d], ext[d], a.face[2 * d], a.face[2 * d + 1]);
+        const int stride = d == 0 ? 1 : d == 1 ? a.nx : nxy;
+        double v[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int k = s == 0 ? 3 : 1;                    // +1, -1
+          const int code = ax.code[k];
+          const int bit = s == 0 ? link_from_plus<Q>(d) : link_from_minus<Q>(d);
+          if (code == ST_INLET) v[s] = a.phi_in[0];
+          else if (code >= 0 || ((gw >> bit) & 1)) v[s] = t0;
+          else v[s] = (double)T[n + (ax.idx[k] - cc[d]) * stride];
+        }
+        const double gd = 0.5 * (v[0] - v[1]) * inv_dT;
+        g2 += gd * gd;
+      }
+      red[0] = sqrt(g2);
+    }
+  }
+  block_sums(red, a.partials + (size_t)blockIdx.x * NSUM);
+}
+
+// Mean and RMS fields from the running statistics (k samples): mean [D+1][N] (u_d, then
+// P_h with P0 added back), rms = sqrt(M2/k).
+static __global__ __launch_bounds__(256) void statistics_kernel(const double *acc, int D, long long N, double k,
+                                                                 double P0, double *mean, double *rms) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  for (int j = 0; j <= D; ++j) {
+    if (mean) mean[j * N + n] = acc[j * N + n] + (j == D ? P0 : 0.0);
+    if (rms) rms[j * N + n] = sqrt(fmax(acc[(D + 1 + j) * N + n], 0.0) / k);
   }
 }
 

@@ -128,6 +128,42 @@ class Solver:
         v = (ctypes.c_double * 3)(*[float(x) for x in pqk])
         self._chk(C.lib().lbm_set_thermo_pressure(self._h, v))
 
+    # ---------------------------------------------------------------- observables
+    def set_statistics(self, every=1):
+        """Start sampling running statistics every `every` levels (None: stop)."""
+        if every is None:
+            self._stats = None
+            self._chk(C.lib().lbm_set_statistics(self._h, None, 1))
+            return
+        self._stats = torch.empty(2 * (self.D + 1) * self.N, dtype=torch.float64, device=self.device)
+        self._chk(C.lib().lbm_set_statistics(self._h, _ptr(self._stats), int(every)))
+
+    def statistics(self):
+        """(mean, rms, samples): mean/rms [D+1, *shape] of (u..., P_h)."""
+        mean = torch.empty((self.D + 1,) + self.shape, dtype=torch.float64, device=self.device)
+        rms = torch.empty_like(mean)
+        k = ctypes.c_int64()
+        self._chk(C.lib().lbm_statistics(self._h, _ptr(mean), _ptr(rms), ctypes.byref(k)))
+        return mean, rms, k.value
+
+    def set_probes(self, cells, capacity):
+        """Record (u..., P_h) at up to 8 cells (linear indices) for `capacity` steps."""
+        cells = [int(c) for c in cells]
+        self._probe = torch.zeros((capacity, len(cells), self.D + 1), dtype=torch.float64, device=self.device)
+        arr = (ctypes.c_int64 * max(len(cells), 1))(*cells)
+        self._chk(C.lib().lbm_set_probes(self._h, arr, len(cells), _ptr(self._probe), int(capacity)))
+
+    def probes(self):
+        rows = ctypes.c_int64()
+        self._chk(C.lib().lbm_probe_rows(self._h, ctypes.byref(rows)))
+        torch.cuda.synchronize(self.device)
+        return self._probe[:rows.value]
+
+    def flame_surface(self, T_u, T_b):
+        v = ctypes.c_double()
+        self._chk(C.lib().lbm_flame_surface(self._h, float(T_u), float(T_b), ctypes.byref(v)))
+        return v.value
+
     def get_state(self):
         pops = torch.empty((self.Q,) + self.shape, dtype=self.pop_dtype, device=self.device)
         scal = torch.empty((self.NS,) + self.shape, dtype=self.scal_dtype, device=self.device)
