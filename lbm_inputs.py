@@ -21,7 +21,8 @@ def base_params(lattice, nx, ny, nz=1, **kw):
              omega_high=1.0, cs_smag=0.0, prandtl=0.7, thickening=1.0, rho_ref=1.0,
              T_ref=300.0, face_bc=list(FACES), inlet_u=[0.0, 0.0, 0.0], inlet_noise=0.0,
              outlet_P=1.0 * CS2, inlet_T=300.0, inlet_Y=[0.0] * 8, weno_scale=[1.0] * 8,
-             chem=[0.0] * 32, seed=2207, pth_mode="open", gamma=1.4)
+             chem=[0.0] * 32, seed=2207, pth_mode="open", gamma=1.4,
+             transport_model="simple", transport=[0.0] * 32)
     p.update(kw)
     return p
 
@@ -67,6 +68,24 @@ def two_step_chem(B1=2.0e4, Ta1=15000.0, B2=2.0e3, Ta2=6000.0, cp=1400.0, phi=0.
     yf, yo, yn = fresh_ch4_air(phi)
     W_ref = mean_W([yf, yo, 0.0, 0.0, 0.0, yn])
     return [B1, Ta1, B2, Ta2, cp] + W_SPECIES + H_SPECIES + [W_ref]
+
+
+def mixture_transport(nu_ref, prandtl=0.7, s_mu=0.7, s_D=1.75):
+    """Placeholder mixture-averaged transport data for CH4, O2, CO, CO2, H2O, N2 (the
+    paper's REGATH data are not available): binary diffusion coefficients in the ratios
+    of typical values at room conditions (relative to O2-N2), scaled so that O2-N2 has
+    the thermal diffusivity nu_ref/Pr at T_ref; linear c_p,k(T) = a_k + b_k T fits
+    (J/kg/K); power-law exponents of mu(T) and D(T).  Layout as the transport array of
+    the parameter set."""
+    rel = {(0, 1): 0.22, (0, 2): 0.22, (0, 3): 0.17, (0, 4): 0.29, (0, 5): 0.22,
+           (1, 2): 0.21, (1, 3): 0.16, (1, 4): 0.26, (1, 5): 0.21,
+           (2, 3): 0.16, (2, 4): 0.26, (2, 5): 0.21,
+           (3, 4): 0.20, (3, 5): 0.16, (4, 5): 0.26}
+    alpha = nu_ref / prandtl
+    D0 = [alpha * rel[(k, j)] / 0.21 for k in range(6) for j in range(k + 1, 6)]
+    a = [1650.0, 878.0, 990.0, 733.0, 1672.0, 990.0]
+    b = [1.9, 0.14, 0.17, 0.39, 0.625, 0.17]
+    return D0 + a + b + [s_mu, s_D, 0.0, 0.0, 0.0]
 
 
 # ----------------------------------------------------------------------------- workloads

@@ -23,7 +23,7 @@ Readings (the paper defers the coupling details to earlier work):
 """
 import torch
 
-from . import curved
+from . import curved, transport
 from .grid import FLUID, INLET, OUTLET, SOLID
 
 
@@ -61,8 +61,11 @@ def w_over_T(params, scal, shape):
     return mixture_W(params, scal[1:]) / scal[0]
 
 
-def viscosity(params, rho):
-    """Molecular kinematic viscosity: constant nu, or constant dynamic viscosity."""
+def viscosity(params, rho, T=None):
+    """Molecular kinematic viscosity: constant nu, constant dynamic viscosity, or (with
+    mixture-averaged transport) the power law of module transport."""
+    if transport.enabled(params):
+        return transport.viscosity(params, T) / rho
     if params["visc_law"] == "const_nu":
         return params["nu_ref"] + torch.zeros_like(rho)
     return params["nu_ref"] * params["rho_ref"] / rho
@@ -216,10 +219,25 @@ def reaction_rates(params, rho, scal):
     return rT, rY
 
 
-def nonadvective_rhs(params, grid, scal, rho):
-    """R_phi = (1/rho) sum_d div_d(rho F D grad phi) + reaction/F, and Lambda (Eq. 3)."""
+def nonadvective_rhs(params, grid, scal, rho, pth=1.0):
+    """R_phi = (1/rho) sum_d div_d(rho F D grad phi) + reaction/F, and Lambda (Eq. 3);
+    with mixture-averaged transport the diffusive parts come from module transport."""
     S = n_scalars(params)
     F = params["thickening"]
+    if transport.enabled(params):
+        phin = inlet_scalars(params)
+        rho_in = density(params, phin.reshape(S, 1, 1, 1), (1, 1, 1), pth).reshape(())
+        RT, RY, cp = transport.rhs(params, grid, scal, rho, phin, rho_in, pth)
+        _, rY = reaction_rates(params, rho, scal)
+        Wk = params["chem"][5:11]
+        rT = -sum(transport.enthalpy(params, scal[0], k) * rY[k] / Wk[k] for k in range(5)) / cp
+        R = [RT + rT / F] + [RY[k] + rY[k] / F for k in range(5)]
+        R = torch.stack(R)
+        Wk = params["chem"][5:11]
+        W = mixture_W(params, scal[1:])
+        R_n2 = -R[1:].sum(0)
+        Lam = R[0] / scal[0] + W * (sum(R[1 + k] / Wk[k] for k in range(5)) + R_n2 / Wk[5])
+        return R, Lam
     nu = viscosity(params, rho)
     rhoD = rho * nu / params["prandtl"]
     phin = inlet_scalars(params)

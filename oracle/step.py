@@ -138,7 +138,7 @@ def _level_n(params, state):
     thermo = _thermo(state)
     rho = scalars.density(params, scal, grid.shape, thermo[0])
     g = pull(params, lat, grid, state["pops"], rho, state["step"])
-    R, Lam = scalars.nonadvective_rhs(params, grid, scal, rho)
+    R, Lam = scalars.nonadvective_rhs(params, grid, scal, rho, thermo[0])
     R, Lam = pressure.apply(params, R, Lam, scal[0] if scal.shape[0] else None, thermo)
     P_h, u = equations.moments(lat, g, rho, Lam)
     if params["physics"] in ("one_step", "two_step"):
@@ -176,7 +176,7 @@ def step(params, state):
     lat, grid, rho, g, R, Lam, P_h, u, grad_rho = _level_n(params, state)
     Xi = equations.source_Xi(lat, rho, u, grad_rho, Lam)
     fp = equations.precondition(g, Xi, rho)
-    nu = scalars.viscosity(params, rho)
+    nu = scalars.viscosity(params, rho, state["scal"][0] if state["scal"].shape[0] else None)
     if params["collision"] == "cumulant":
         fps, _ = cumulant.cumulant_collide(lat, fp, u, nu, params["cs_smag"],
                                            params["omega_bulk"], params["omega_high"])
