@@ -74,6 +74,7 @@ enum { LBM_ISOTHERMAL = 0, LBM_PASSIVE = 1, LBM_ONE_STEP = 2, LBM_TWO_STEP = 3 }
 enum { LBM_VISC_CONST_NU = 0, LBM_VISC_CONST_MU = 1 };
 enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_INLET = 2, LBM_OUTLET = 3 };
 enum { LBM_PTH_OPEN = 0, LBM_PTH_CLOSED = 1 };
+enum { LBM_TRANSPORT_SIMPLE = 0, LBM_TRANSPORT_MIXTURE = 1 };
 
 /* Problem statement (Sec. 2 and 3 of the paper), lattice units. */
 typedef struct {
@@ -102,7 +103,22 @@ typedef struct {
   uint64_t seed;      /* counter-based inlet noise (SplitMix64) */
   int32_t pth_mode;   /* LBM_PTH_OPEN (constant P_th, Eq. 3) | LBM_PTH_CLOSED (mass held) */
   double gamma;       /* ratio of specific heats (closed domains; must exceed 1) */
+  int32_t transport_model; /* LBM_TRANSPORT_SIMPLE (unity Lewis, constant c_p) |
+                              LBM_TRANSPORT_MIXTURE (LBM_TWO_STEP only, see below) */
+  double transport[32];    /* mixture data: binary D0_kj at T_ref for pairs k < j of
+                              (CH4, O2, CO, CO2, H2O, N2) in the order (0,1) (0,2) .. (4,5)
+                              [0..14], c_p,k = a_k + b_k T: a [15..20], b [21..26] (J/kg/K),
+                              exponents s_mu [27], s_D [28] */
 } lbm_params;
+
+/* Mixture-averaged transport (the paper evaluates its thermodynamic and transport
+ * properties with mixture-averaged approximations, Sec. 2.3; the module and data are
+ * not given, read as follows): mu = nu_ref rho_ref (T/T_ref)^s_mu, c_p = sum Y_k c_p,k(T),
+ * lambda = mu c_p / Pr; D_kj = D0_kj (T/T_ref)^s_D / pi; D_k = (1 - Y_k)/sum_{j!=k} X_j/D_kj;
+ * face fluxes J*_k = -(rho D_k W_k/W)_f (X_k,nb - X_k), J_k = J*_k - (Y_k)_f sum_j J*_j
+ * (face values: means of the two cells); R_T = F/(rho c_p) div(lambda grad T) plus the
+ * heat release -sum_k h_k(T) omega_k/(F rho c_p) with h_k(T) = h0_k + W_k int_{298.15}^T
+ * c_p,k; R_k = -(F/rho) div J_k + omega_k/(F rho); the LB viscosity is mu(T)/rho. */
 
 /* Sizes (bytes) of the caller-provided device buffers for these parameters: one
  * population array (two are needed, A and B), one scalar array (two needed), and the

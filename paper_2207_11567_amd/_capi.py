@@ -19,6 +19,7 @@ PHYSICS = {"isothermal": 0, "passive": 1, "one_step": 2, "two_step": 3}
 VISC = {"const_nu": 0, "const_mu": 1}
 FACE = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
 PTH = {"open": 0, "closed": 1}
+TRANSPORT = {"simple": 0, "mixture": 1}
 N_SCALARS = {"isothermal": 0, "passive": 1, "one_step": 2, "two_step": 6}
 
 
@@ -32,7 +33,8 @@ class LbmParams(ctypes.Structure):
                 ("face_bc", c_int32 * 6), ("inlet_u", c_double * 3), ("inlet_noise", c_double),
                 ("outlet_P", c_double), ("inlet_T", c_double), ("inlet_Y", c_double * 8),
                 ("weno_scale", c_double * 8), ("chem", c_double * 32), ("seed", c_uint64),
-                ("pth_mode", c_int32), ("gamma", c_double)]
+                ("pth_mode", c_int32), ("gamma", c_double),
+                ("transport_model", c_int32), ("transport", c_double * 32)]
 
 
 def make_params(d):
@@ -60,6 +62,9 @@ def make_params(d):
     p.seed = int(d["seed"]) & 0xFFFFFFFFFFFFFFFF
     p.pth_mode = PTH[d.get("pth_mode", "open")]
     p.gamma = float(d.get("gamma", 1.4))
+    p.transport_model = TRANSPORT[d.get("transport_model", "simple")]
+    for i, v in enumerate(list(d.get("transport", [0.0] * 32))[:32]):
+        p.transport[i] = float(v)
     return p
 
 

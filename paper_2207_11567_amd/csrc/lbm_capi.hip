@@ -103,6 +103,15 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   for (int f = 0; f < 6; ++f)
     if (p->face_bc[f] < LBM_PERIODIC || p->face_bc[f] > LBM_OUTLET) return fail("unknown face condition");
   if (p->pth_mode != LBM_PTH_OPEN && p->pth_mode != LBM_PTH_CLOSED) return fail("unknown pth_mode");
+  if (p->transport_model != LBM_TRANSPORT_SIMPLE && p->transport_model != LBM_TRANSPORT_MIXTURE)
+    return fail("unknown transport_model");
+  if (p->transport_model == LBM_TRANSPORT_MIXTURE) {
+    if (p->physics != LBM_TWO_STEP) return fail("mixture-averaged transport needs the two-step scalars");
+    for (int k = 0; k < 15; ++k)
+      if (!(p->transport[k] > 0.0) || !isfinite(p->transport[k])) return fail("mixture transport: D0_kj must be > 0");
+    for (int k = 0; k < 6; ++k)
+      if (!(p->transport[15 + k] > 0.0)) return fail("mixture transport: c_p coefficients a_k must be > 0");
+  }
   if (p->pth_mode == LBM_PTH_CLOSED) {
     if (!(p->gamma > 1.0) || !isfinite(p->gamma)) return fail("closed domain needs gamma > 1");
     for (int f = 0; f < 2 * Dm; ++f)
@@ -140,6 +149,38 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
 static lbm_status hip_fail(lbm_solver *s, hipError_t e, const char *what) {
   s->err = std::string(what) + ": " + hipGetErrorString(e);
   return LBM_E_HIP;
+}
+
+// The inlet state's mixture transport point (FP64, same formulas as the kernel's).
+static void mix_inlet_point(const lbm_params &p, double *out) {
+  const double *ch = p.chem, *tr = p.transport;
+  double Y[6], ys = 0.0;
+  for (int k = 0; k < 5; ++k) {
+    Y[k] = p.inlet_Y[k];
+    ys += Y[k];
+  }
+  Y[5] = 1.0 - ys;
+  double invW = 0.0;
+  for (int k = 0; k < 6; ++k) invW += Y[k] / ch[5 + k];
+  const double T = p.inlet_T, rho = p.rho_ref * (p.T_ref / T) / (invW * ch[17]);
+  const double lt = log(T / p.T_ref), mu = p.nu_ref * p.rho_ref * exp(tr[27] * lt), scale = exp(tr[28] * lt);
+  double cp = 0.0, X[6];
+  for (int k = 0; k < 6; ++k) {
+    cp += Y[k] * (tr[15 + k] + tr[21 + k] * T);
+    X[k] = Y[k] / (invW * ch[5 + k]);
+  }
+  out[0] = mu * cp / p.prandtl;
+  double B[6][6];
+  for (int i = 0, n = 0; i < 6; ++i)
+    for (int j = i + 1; j < 6; ++j, ++n) B[i][j] = B[j][i] = tr[n];
+  for (int k = 0; k < 6; ++k) {
+    double sum = 0.0;
+    for (int j = 0; j < 6; ++j)
+      if (j != k) sum += X[j] / B[k][j];
+    out[1 + k] = rho * (1.0 - Y[k]) * scale / sum * ch[5 + k] * invW;
+    out[7 + k] = X[k];
+    out[13 + k] = Y[k];
+  }
 }
 
 static StepArgs make_args(const lbm_solver *s) {
@@ -189,6 +230,9 @@ static StepArgs make_args(const lbm_solver *s) {
   a.th.F = s->NS > 0 ? p.thickening : 1.0;
   a.th.visc_const_mu = p.visc_law == LBM_VISC_CONST_MU ? 1.0 : 0.0;
   for (int k = 0; k < 32; ++k) a.th.chem[k] = p.chem[k];
+  a.mix = p.transport_model == LBM_TRANSPORT_MIXTURE ? 1 : 0;
+  for (int k = 0; k < 32; ++k) a.transport[k] = p.transport[k];
+  if (a.mix) mix_inlet_point(p, a.mix_in);
   return a;
 }
 

@@ -323,6 +323,56 @@ template <class R> struct ThermoT {
 };
 
 
+// Mixture-averaged transport for the two-step scalars (species CH4, O2, CO, CO2, H2O, N2):
+// binary coefficients D_kj = D0_kj (T/T_ref)^sD / pi, c_p,k = a_k + b_k T, mu ~ T^smu.
+template <class R> struct MixT {
+  int on;
+  R invB[6][6];          // 1/D0_kj (diagonal 0)
+  R cpa[6], cpb[6];
+  R s_mu, s_D, inv_Tref;
+  R hc[6];               // h_k(T) = hc_k + W_k T (a_k + b_k T / 2)
+  R in_kap, in_coef[6], in_X[6], in_Y[6];   // the inlet state's transport point
+};
+
+// Transport point of a cell state: lambda = mu c_p / Pr, rho D_k W_k/W (Hirschfelder-
+// Curtiss D_k = (1 - Y_k)/sum_{j != k} X_j/D_kj), mole and mass fractions; mu and c_p.
+template <class R> struct MixPoint {
+  R kap, coef[6], X[6], Y[6];
+};
+template <class R>
+__device__ __forceinline__ void mix_point(const MixT<R> &m, const ThermoT<R> &th, const R (&v)[6], R rho, R pi,
+                                          MixPoint<R> &o, R &mu, R &cp) {
+  R ys = R(0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    o.Y[k] = v[1 + k];
+    ys += v[1 + k];
+  }
+  o.Y[5] = R(1) - ys;
+  R invW = R(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) invW += o.Y[k] * th.inv_W[k];
+  const R W = fdiv(R(1), invW);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) o.X[k] = o.Y[k] * W * th.inv_W[k];
+  const R T = v[0];
+  const R lt = log(T * m.inv_Tref);
+  mu = th.mu_ref * exp(m.s_mu * lt);
+  const R scale = fdiv(exp(m.s_D * lt), pi);
+  cp = R(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) cp += o.Y[k] * (m.cpa[k] + m.cpb[k] * T);
+  o.kap = mu * cp * th.inv_Pr;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    R sum = R(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j != k) sum += o.X[j] * m.invB[k][j];
+    o.coef[k] = rho * fdiv((R(1) - o.Y[k]) * scale, sum) * th.W[k] * invW;
+  }
+}
+
 // Ideal-gas density at the thermodynamic pressure pi P_th(0) (pi = 1 in open domains).
 template <int NS, class R>
 __device__ __forceinline__ R density(const ThermoT<R> &t, const R (&v)[NS > 0 ? NS : 1], R pi = R(1)) {

@@ -36,7 +36,7 @@ template <int Q, int PREC, int NS>
 hipError_t launch_one(int kind, const StepArgs &a, int nblocks, hipStream_t st, const double *Ph,
                       const double *u, const double *scal) {
   using R = typename Prec<PREC>::R;
-  const bool full = a.lvl || a.stats || a.probe_out;
+  const bool full = a.lvl || a.stats || a.probe_out || a.mix;
   if (kind == LAUNCH_STEP && full)
     hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, true>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
   else if (kind == LAUNCH_STEP)

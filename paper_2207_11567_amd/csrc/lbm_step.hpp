@@ -51,6 +51,9 @@ struct StepArgs {
   double *probe_out;   // row of this level in the probe record ([nprobe][D+1]) or nullptr
   int nprobe;
   int probe[8];        // probe cells
+  int mix;             // mixture-averaged transport (two-step scalars)
+  double transport[32];  // binary D0 (15), c_p a_k (6), b_k (6), exponents of mu and D
+  double mix_in[19];   // inlet transport point: lambda, rho D_k W_k/W (6), X_k (6), Y_k (6)
   double *f_P, *f_rho, *f_u, *f_scal;   // field outputs (extract mode)
   int nx, ny, nz;
   long long N;
@@ -97,6 +100,7 @@ template <class R> struct KArgs {
   unsigned long long seed;
   double inv_T_ref_d, W_d[6];
   ThermoT<R> th;
+  MixT<R> mx;
 };
 
 template <class R> KArgs<R> to_kargs(const StepArgs &a) {
@@ -131,6 +135,28 @@ template <class R> KArgs<R> to_kargs(const StepArgs &a) {
     t.W[q] = (R)ch[5 + q];
     t.inv_W[q] = (R)(ch[5 + q] > 0.0 ? 1.0 / ch[5 + q] : 0.0);
     t.h[q] = (R)ch[11 + q];
+  }
+  MixT<R> &m = k.mx;
+  m.on = a.mix;
+  const double *tr = a.transport;
+  for (int i = 0, n = 0; i < 6; ++i) {
+    m.invB[i][i] = R(0);
+    for (int j = i + 1; j < 6; ++j, ++n) m.invB[i][j] = m.invB[j][i] = (R)(tr[n] > 0.0 ? 1.0 / tr[n] : 0.0);
+  }
+  const double T0 = 298.15;     // reference temperature of the formation enthalpies
+  for (int q = 0; q < 6; ++q) {
+    m.cpa[q] = (R)tr[15 + q];
+    m.cpb[q] = (R)tr[21 + q];
+    m.hc[q] = (R)(ch[11 + q] - ch[5 + q] * (tr[15 + q] * T0 + 0.5 * tr[21 + q] * T0 * T0));
+  }
+  m.s_mu = (R)tr[27];
+  m.s_D = (R)tr[28];
+  m.inv_Tref = (R)(1.0 / a.th.T_ref);
+  m.in_kap = (R)a.mix_in[0];
+  for (int q = 0; q < 6; ++q) {
+    m.in_coef[q] = (R)a.mix_in[1 + q];
+    m.in_X[q] = (R)a.mix_in[7 + q];
+    m.in_Y[q] = (R)a.mix_in[13 + q];
   }
   return k;
 }
@@ -362,6 +388,54 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
       const R rho0 = NS > 0 ? density<NS, R>(a.th, phi0, pim) : R(a.th.rho_ref);
       const R rho_in = NS > 0 ? density<NS, R>(a.th, phin, pim) : R(a.th.rho_ref);
 
+      // mixture-averaged diffusion (Hirschfelder-Curtiss fluxes with the correction flux,
+      // lambda grad T), formed before the populations are pulled to keep registers free
+      R R_s[NSV];
+#pragma unroll
+      for (int k = 0; k < NSV; ++k) R_s[k] = R(0);
+      R mu_c = R(0), cp_c = R(1);
+      if constexpr (FULL && NS == 6) {
+        if (a.mx.on) {
+          MixPoint<R> mc;
+          mix_point<R>(a.mx, a.th, phi0, rho0, pim, mc, mu_c, cp_c);
+          for (int d = 0; d < D; ++d) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+              const int sn = status(d, side == 0 ? 1 : -1);
+              if (sn != ST_FLUID && sn != ST_INLET) continue;
+              MixPoint<R> mn;
+              R vn[NSV];
+              if (sn == ST_FLUID) {
+                const unsigned mq = un + (unsigned)off[d][side == 0 ? 3 : 1];
+#pragma unroll
+                for (int q = 0; q < NS; ++q) vn[q] = (R)ldg(sin_ + (size_t)q * N, mq);
+                R mu_n, cp_n;
+                mix_point<R>(a.mx, a.th, vn, density<NS, R>(a.th, vn, pim), pim, mn, mu_n, cp_n);
+              } else {
+#pragma unroll
+                for (int q = 0; q < NS; ++q) vn[q] = phin[q];
+                mn.kap = a.mx.in_kap;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                  mn.coef[k] = a.mx.in_coef[k];
+                  mn.X[k] = a.mx.in_X[k];
+                  mn.Y[k] = a.mx.in_Y[k];
+                }
+              }
+              R_s[0] += R(0.5) * (mc.kap + mn.kap) * (vn[0] - phi0[0]);
+              R J[6], Js = R(0);
+#pragma unroll
+              for (int k = 0; k < 6; ++k) {
+                J[k] = -R(0.5) * (mc.coef[k] + mn.coef[k]) * (mn.X[k] - mc.X[k]);
+                Js += J[k];
+              }
+#pragma unroll
+              for (int k = 0; k < 5; ++k) R_s[1 + k] -= J[k] - R(0.5) * (mc.Y[k] + mn.Y[k]) * Js;
+            }
+          }
+        }
+      }
+
       // ---------------------------------------------------------------- pull (Eq. 1)
       R gh[Q];
       const bool border = code[0][1] >= 0 || code[0][3] >= 0 || code[1][1] >= 0 || code[1][3] >= 0 ||
@@ -476,9 +550,9 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
       // centred diffusion fluxes and the WENO3 advective derivative.
       R gradrho[3] = {R(0), R(0), R(0)};
       R Lam = R(0);
-      R R_s[NSV], adv[NSV];
+      R adv[NSV];
 #pragma unroll
-      for (int k = 0; k < NSV; ++k) { R_s[k] = R(0); adv[k] = R(0); }
+      for (int k = 0; k < NSV; ++k) adv[k] = R(0);
       if constexpr (NS > 0) {
         const R rhoD0 = rho0 * viscosity(a.th, rho0) * a.th.inv_Pr;
         const R rhoD_in = rho_in * viscosity(a.th, rho_in) * a.th.inv_Pr;
@@ -564,8 +638,11 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
               cfp = fp ? R(0.5) * (rhoD0 + (sp1 == ST_INLET ? rhoD_in : rp * viscosity(a.th, rp) * a.th.inv_Pr)) : R(0);
               cfm = fm ? R(0.5) * (rhoD0 + (sm1 == ST_INLET ? rhoD_in : rm * viscosity(a.th, rm) * a.th.inv_Pr)) : R(0);
             }
+            const bool mixed = FULL && NS == 6 && a.mx.on;   // diffusion done before the pull
+            if (!mixed) {
 #pragma unroll
-            for (int q = 0; q < NS; ++q) R_s[q] += cfp * (vp1[q] - phi0[q]) + cfm * (vm1[q] - phi0[q]);
+              for (int q = 0; q < NS; ++q) R_s[q] += cfp * (vp1[q] - phi0[q]) + cfm * (vm1[q] - phi0[q]);
+            }
             if (!EXTRACT) {
               // WENO3 upwinded on the sign of u_d, written branch-free: with the upwind
               // neighbours U1, U2 and the downwind neighbour D1,
@@ -603,6 +680,9 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
         const R Fr = fdiv(a.th.F, rho0);
 #pragma unroll
         for (int q = 0; q < NS; ++q) R_s[q] *= Fr;
+        if constexpr (FULL && NS == 6) {
+          if (a.mx.on) R_s[0] = fdiv(R_s[0], cp_c);
+        }
         // chemistry (reaction over F) and Lambda (Eq. 3)
         const R invF = a.th.invF;
         if constexpr (NS == 2) {
@@ -629,8 +709,18 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           R_s[3] += a.th.W[2] * m2 * invF;
           R_s[4] += a.th.W[3] * m3 * invF;
           R_s[5] += a.th.W[4] * m4 * invF;
-          const R heat = -(a.th.h[0] * m0 + a.th.h[1] * m1 + a.th.h[2] * m2 + a.th.h[3] * m3 +
-                           a.th.h[4] * m4) * a.th.inv_cp;
+          R heat = -(a.th.h[0] * m0 + a.th.h[1] * m1 + a.th.h[2] * m2 + a.th.h[3] * m3 +
+                     a.th.h[4] * m4) * a.th.inv_cp;
+          if constexpr (FULL) {
+            if (a.mx.on) {
+              // full molar enthalpies h_k(T) and the mixture c_p
+              R hT[5];
+#pragma unroll
+              for (int q = 0; q < 5; ++q)
+                hT[q] = a.mx.hc[q] + a.th.W[q] * T * (a.mx.cpa[q] + R(0.5) * a.mx.cpb[q] * T);
+              heat = -fdiv(hT[0] * m0 + hT[1] * m1 + hT[2] * m2 + hT[3] * m3 + hT[4] * m4, cp_c);
+            }
+          }
           R_s[0] += heat * invF;
           if (a.thermo) R_s[0] += a.kap * qn * T;         // pressure work
           // Lambda = R_T/T + W sum_k R_k/W_k (N2 by closure: R_N2 = -sum R_k)
@@ -730,7 +820,10 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) e[i] -= R(wgt<Q>(i)) * Es;   // d = f~ - w
-        const R nu = viscosity(a.th, rho0);
+        R nu = viscosity(a.th, rho0);
+        if constexpr (FULL && NS == 6) {
+          if (a.mx.on) nu = fdiv(mu_c, rho0);
+        }
         Rates<R> rt;
         rt.tau0 = nu * R(3) + R(0.5);                    // nu / cs2 + 1/2
         rt.smag18 = a.smag18;
