@@ -205,8 +205,11 @@ __device__ __forceinline__ AxisNb axis_nb(int c, int n, int flo, int fhi) {
     } else if (p >= n) {
       if (fhi < 0) p -= n; else code = fhi;
     }
-    // very small periodic extents: wrap again
-    if (code < 0) { p = ((p % n) + n) % n; }
+    // extents of one cell: wrap a second time (|k| <= 2), no division
+    if (code < 0) {
+      if (p < 0) p += n;
+      if (p >= n) p -= n;
+    }
     r.idx[k + 2] = code < 0 ? p : c;
     r.code[k + 2] = code;
   }
@@ -228,6 +231,31 @@ template <class T> __device__ __forceinline__ T ldg_nt(const T *base, unsigned i
 }
 template <class T> __device__ __forceinline__ void stg_nt(T *base, unsigned idx, T v) {
   __builtin_nontemporal_store(v, (T *)((char *)base + idx * (unsigned)sizeof(T)));
+}
+
+// Raw buffer access: one descriptor (SGPRs) per array slice (a population or a scalar
+// field, under 4 GiB since Q N < 2^31 elements) and a 32-bit byte offset per lane, so the
+// neighbours of a cell share offset registers and no load needs 64-bit address arithmetic.
+// AUX 2 marks a streaming (non-temporal) access.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slice(const void *p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, -1, 0x00020000);
+}
+template <class T, int AUX = 0> __device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, unsigned idx) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8u, 0, AUX));
+  else if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4u, 0, AUX));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, idx * 2u, 0, AUX));
+}
+template <class T, int AUX = 0> __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned idx, T v) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, idx * 8u, 0, AUX);
+  else if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, idx * 4u, 0, AUX);
+  else
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, idx * 2u, 0, AUX);
 }
 
 // (1 - p) a + p b, exact at p = 0 and p = 1.
@@ -297,18 +325,24 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
   // Banded tile order: 64x4-cell tiles, visited band of rows by band, and inside a band
   // plane by plane, so the +-1 and +-2 planes of the scalar stencils were touched a few
   // dozen tiles earlier and are still in L2.
-  int n;
+  int n, x, y, z;
   if (a.band_rows) {
     const int nxt = a.nx >> 6, bt = a.band_rows >> 2;
     const int per_plane = nxt * bt, per_band = per_plane * a.nz;
     const int band = tile / per_band, r = tile - band * per_band;
     const int zz = r / per_plane, r2 = r - zz * per_plane;
     const int xt = r2 / bt, ys = r2 - xt * bt;
-    const int xx = (xt << 6) + ((int)threadIdx.x & 63);
-    const int yy = band * a.band_rows + (ys << 2) + ((int)threadIdx.x >> 6);
-    n = xx + a.nx * (yy + a.ny * zz);
+    x = (xt << 6) + ((int)threadIdx.x & 63);
+    y = band * a.band_rows + (ys << 2) + ((int)threadIdx.x >> 6);
+    z = zz;
+    n = x + a.nx * (y + a.ny * z);
   } else {
     n = tile * (int)blockDim.x + (int)threadIdx.x;
+    const int nxy = a.nx * a.ny;
+    z = n / nxy;
+    const int rem = n - z * nxy;
+    y = rem / a.nx;
+    x = rem - y * a.nx;
   }
   double red[NSUM] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int N = a.N;
@@ -320,10 +354,6 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
 
   if (n < N) {
     const int nxy = a.nx * a.ny;
-    const int z = n / nxy;
-    const int rem = n - z * nxy;
-    const int y = rem / a.nx;
-    const int x = rem - y * a.nx;
     const GW gw = a.geom ? ((const GW *)a.geom)[n] : GW(0);
     if (gw & (GW(1) << bit_self<Q>())) {
       if (!EXTRACT) {
@@ -384,7 +414,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
 #pragma unroll
       for (int k = 0; k < NSV; ++k) { phi0[k] = R(0); phin[k] = R(a.phi_in[k]); }
 #pragma unroll
-      for (int k = 0; k < NS; ++k) phi0[k] = (R)ldg(sin_ + (size_t)k * N, un);
+      for (int k = 0; k < NS; ++k) phi0[k] = (R)bld<Sc>(slice(sin_ + (size_t)k * N), un);
       const R rho0 = NS > 0 ? density<NS, R>(a.th, phi0, pim) : R(a.th.rho_ref);
       const R rho_in = NS > 0 ? density<NS, R>(a.th, phin, pim) : R(a.th.rho_ref);
 
@@ -408,7 +438,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
               if (sn == ST_FLUID) {
                 const unsigned mq = un + (unsigned)off[d][side == 0 ? 3 : 1];
 #pragma unroll
-                for (int q = 0; q < NS; ++q) vn[q] = (R)ldg(sin_ + (size_t)q * N, mq);
+                for (int q = 0; q < NS; ++q) vn[q] = (R)bld<Sc>(slice(sin_ + (size_t)q * N), mq);
                 R mu_n, cp_n;
                 mix_point<R>(a.mx, a.th, vn, density<NS, R>(a.th, vn, pim), pim, mn, mu_n, cp_n);
               } else {
@@ -445,7 +475,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const unsigned m = un + (unsigned)(off[0][2 - cx(i)] + off[1][2 - cy(i)] + (D == 3 ? off[2][2 - cz(i)] : 0));
-          gh[i] = decode<R>(ldg_nt(pin + (size_t)i * N, m));
+          gh[i] = decode<R>(bld<St, 2>(slice(pin + (size_t)i * N), m));
         }
       } else {
         // boundary cell: bounce-back, moving-wall inlet, anti-bounce-back outlet
@@ -471,7 +501,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
         if (has_out) {
 #pragma unroll
           for (int j = 0; j < Q; ++j) {
-            const R gj = decode<R>(ldg(pin + (size_t)j * N, un));
+            const R gj = decode<R>(bld<St>(slice(pin + (size_t)j * N), un));
             uo[0] += R(cx(j)) * gj;
             uo[1] += R(cy(j)) * gj;
             if (D == 3) uo[2] += R(cz(j)) * gj;
@@ -496,7 +526,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           const bool solid_src = (gw >> i) & 1;
           const int io = Q - 1 - i;
           if (wall || (!inl && !outl && solid_src)) {
-            const R gopp = decode<R>(ldg(pin + (size_t)io * N, un));
+            const R gopp = decode<R>(bld<St>(slice(pin + (size_t)io * N), un));
             gh[i] = gopp;
             if (FULL && !wall && a.lvl) {
               // interpolated bounce-back, the wall at the fraction q of the link to r - c_i
@@ -510,23 +540,23 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
                   if (c[d] != 0 && code[d][2 + c[d]] >= 0) ahead_fluid = false;
                 if (ahead_fluid) {
                   const unsigned ma = un + (unsigned)(off[0][2 + c[0]] + off[1][2 + c[1]] + (D == 3 ? off[2][2 + c[2]] : 0));
-                  gh[i] = lerp(decode<R>(ldg(pin + (size_t)io * N, ma)), gopp, R(2) * qf);
+                  gh[i] = lerp(decode<R>(bld<St>(slice(pin + (size_t)io * N), ma)), gopp, R(2) * qf);
                 }
               } else {
                 const R h = fdiv(R(1), R(2) * qf);
-                gh[i] = gopp * h + (R(1) - h) * decode<R>(ldg(pin + (size_t)i * N, un));
+                gh[i] = gopp * h + (R(1) - h) * decode<R>(bld<St>(slice(pin + (size_t)i * N), un));
               }
             }
           } else if (inl) {
             const R cu = R(c[0]) * uw_in[0] + R(c[1]) * uw_in[1] + R(c[2]) * uw_in[2];
-            gh[i] = decode<R>(ldg(pin + (size_t)io * N, un)) + R(2.0 * wgt<Q>(i)) * rho_in * cu * invP0;
+            gh[i] = decode<R>(bld<St>(slice(pin + (size_t)io * N), un)) + R(2.0 * wgt<Q>(i)) * rho_in * cu * invP0;
           } else if (outl) {
             const R cu = R(c[0]) * uo[0] + R(c[1]) * uo[1] + R(c[2]) * uo[2];
-            gh[i] = -decode<R>(ldg(pin + (size_t)io * N, un)) +
+            gh[i] = -decode<R>(bld<St>(slice(pin + (size_t)io * N), un)) +
                     R(2.0 * wgt<Q>(i)) * ((R(a.outlet_P) + rho0 * (cu * cu * R(1.5) - uo2 * R(0.5))) * invP0 - R(1));
           } else {
             const unsigned m = un + (unsigned)(off[0][2 - c[0]] + off[1][2 - c[1]] + (D == 3 ? off[2][2 - c[2]] : 0));
-            gh[i] = decode<R>(ldg_nt(pin + (size_t)i * N, m));
+            gh[i] = decode<R>(bld<St, 2>(slice(pin + (size_t)i * N), m));
           }
         }
       }
@@ -576,11 +606,11 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             for (int q = 0; q < NS; ++q) {
               const Sc *sq = sin_ + (size_t)q * N;
               if (FAST) {
-                vp1[q] = (R)ldg(sq, mp1);
-                vm1[q] = (R)ldg(sq, mm1);
+                vp1[q] = (R)bld<Sc>(slice(sq), mp1);
+                vm1[q] = (R)bld<Sc>(slice(sq), mm1);
               } else {
-                vp1[q] = sp1 == ST_FLUID ? (R)ldg(sq, mp1) : sp1 == ST_INLET ? phin[q] : phi0[q];
-                vm1[q] = sm1 == ST_FLUID ? (R)ldg(sq, mm1) : sm1 == ST_INLET ? phin[q] : phi0[q];
+                vp1[q] = sp1 == ST_FLUID ? (R)bld<Sc>(slice(sq), mp1) : sp1 == ST_INLET ? phin[q] : phi0[q];
+                vm1[q] = sm1 == ST_FLUID ? (R)bld<Sc>(slice(sq), mm1) : sm1 == ST_INLET ? phin[q] : phi0[q];
               }
             }
             // curved walls: mirror images of solid cells at -1 / +1 (c1), of the stencil
@@ -655,16 +685,16 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
                 const R v0 = phi0[q];
                 R vU2;
                 if (FAST) {
-                  vU2 = (R)ldg(sq, mfar);
+                  vU2 = (R)bld<Sc>(slice(sq), mfar);
                 } else {
                   R vm2, vp2;
-                  if (sm1 == ST_FLUID) vm2 = sm2 == ST_FLUID ? (R)ldg(sq, mm2) : sm2 == ST_INLET ? phin[q] : vm1[q];
+                  if (sm1 == ST_FLUID) vm2 = sm2 == ST_FLUID ? (R)bld<Sc>(slice(sq), mm2) : sm2 == ST_INLET ? phin[q] : vm1[q];
                   else vm2 = sm1 == ST_SOLID ? vp1[q] : sm1 == ST_INLET ? phin[q] : v0;
-                  if (sp1 == ST_FLUID) vp2 = sp2 == ST_FLUID ? (R)ldg(sq, mp2) : sp2 == ST_INLET ? phin[q] : vp1[q];
+                  if (sp1 == ST_FLUID) vp2 = sp2 == ST_FLUID ? (R)bld<Sc>(slice(sq), mp2) : sp2 == ST_INLET ? phin[q] : vp1[q];
                   else vp2 = sp1 == ST_SOLID ? vm1[q] : sp1 == ST_INLET ? phin[q] : v0;
-                  if (c2m) vm2 = p2m <= R(1) ? lerp(v0, vp1[q], p2m) : lerp(vp1[q], (R)ldg(sq, mp2), p2m - R(1));
+                  if (c2m) vm2 = p2m <= R(1) ? lerp(v0, vp1[q], p2m) : lerp(vp1[q], (R)bld<Sc>(slice(sq), mp2), p2m - R(1));
                   else if (c3m) vm2 = lerp(vm1[q], v0, w3m);
-                  if (c2p) vp2 = p2p <= R(1) ? lerp(v0, vm1[q], p2p) : lerp(vm1[q], (R)ldg(sq, mm2), p2p - R(1));
+                  if (c2p) vp2 = p2p <= R(1) ? lerp(v0, vm1[q], p2p) : lerp(vm1[q], (R)bld<Sc>(slice(sq), mm2), p2p - R(1));
                   else if (c3p) vp2 = lerp(vp1[q], v0, w3p);
                   vU2 = up ? vm2 : vp2;
                 }
@@ -781,7 +811,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
         for (int q = 0; q < NS; ++q) {
           const R nv = phi0[q] + (R_s[q] - adv[q]);
           bad |= !isfinite(nv);
-          stg(sout + (size_t)q * N, un, (Sc)nv);
+          bst<Sc>(slice(sout + (size_t)q * N), un, (Sc)nv);
           phi1[q] = (R)(Sc)nv;
         }
         if (a.thermo) red[8] = w_over_T<NS>(a.th, phi1, a.inv_T_ref_d);
@@ -841,7 +871,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             R gs;
             if constexpr (NS >= 2) gs = R(wgt<Q>(i)) * base + e[i] * invr + Xi[i] * hP0;   // Eq. 8
             else gs = R(wgt<Q>(i)) * base + e[i];
-            stg_nt(pout + (size_t)i * N, un, encode<St>(gs));
+            bst<St, 2>(slice(pout + (size_t)i * N), un, encode<St>(gs));
           }
         } else {
           // BGK in the pre-conditioned frame (Eq. 5 with the half-source split)
@@ -855,7 +885,7 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             R xh = R(0);
             if constexpr (NS >= 2) xh = Xi[i] * hP0;
             const R gp = gh[i] + xh;
-            stg_nt(pout + (size_t)i * N, un, encode<St>(gp - om * (gp - geq) + xh));
+            bst<St, 2>(slice(pout + (size_t)i * N), un, encode<St>(gp - om * (gp - geq) + xh));
           }
         }
         bad |= !isfinite(Ph + u[0] + u[1] + u[2]);
