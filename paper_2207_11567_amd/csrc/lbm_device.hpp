@@ -320,6 +320,7 @@ template <class R> struct ThermoT {
   R heat1;               // one-step: (T_ad - T_u)/Y_u
   R inv_cp;
   R W[6], inv_W[6], h[6];
+  R dinv_W[5];           // 1/W_k - 1/W_N2: 1/W = 1/W_N2 + sum_k Y_k (1/W_k - 1/W_N2)
 };
 
 
@@ -382,13 +383,9 @@ __device__ __forceinline__ R density(const ThermoT<R> &t, const R (&v)[NS > 0 ? 
     return fdiv(t.rhoT * pi, v[0]);
   } else {
     // rho = rho_ref (T_ref/T)(W/W_ref), 1/W = sum Y_k/W_k with N2 by closure
-    R ysum = R(0), inv = R(0);
+    R inv = t.inv_W[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      ysum += v[1 + k];
-      inv += v[1 + k] * t.inv_W[k];
-    }
-    inv += (R(1) - ysum) * t.inv_W[5];
+    for (int k = 0; k < 5; ++k) inv += v[1 + k] * t.dinv_W[k];
     return fdiv(t.rhoT_W * pi, v[0] * inv);
   }
 }

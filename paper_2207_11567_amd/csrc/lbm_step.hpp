@@ -136,6 +136,8 @@ template <class R> KArgs<R> to_kargs(const StepArgs &a) {
     t.inv_W[q] = (R)(ch[5 + q] > 0.0 ? 1.0 / ch[5 + q] : 0.0);
     t.h[q] = (R)ch[11 + q];
   }
+  for (int q = 0; q < 5; ++q)
+    t.dinv_W[q] = (R)(ch[5 + q] > 0.0 && ch[10] > 0.0 ? 1.0 / ch[5 + q] - 1.0 / ch[10] : 0.0);
   MixT<R> &m = k.mx;
   m.on = a.mix;
   const double *tr = a.transport;
@@ -214,6 +216,26 @@ __device__ __forceinline__ AxisNb axis_nb(int c, int n, int flo, int fhi) {
     r.code[k + 2] = code;
   }
   return r;
+}
+
+// Offsets (times the axis stride) and face codes of positions c-2..c+2 on one axis; cells at
+// least two away from both ends take the plain offsets without any wrap logic.
+__device__ __forceinline__ void axis_offsets(int c, int n, int flo, int fhi, int stride, int (&off)[5],
+                                             int (&code)[5]) {
+  if (c >= 2 && c < n - 2) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      off[k] = (k - 2) * stride;
+      code[k] = -1;
+    }
+  } else {
+    const AxisNb A = axis_nb(c, n, flo, fhi);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      off[k] = (A.idx[k] - c) * stride;
+      code[k] = A.code[k];
+    }
+  }
 }
 
 // Element access through a wave-uniform base pointer and a 32-bit byte offset, so that
@@ -299,10 +321,9 @@ __device__ __forceinline__ double w_over_T(const ThermoT<R> &t, const R (&v)[NS 
   } else if constexpr (NS == 2) {
     return (double)fdiv(R(1), v[0]);
   } else {
-    R ys = R(0), inv = R(0);
+    R inv = t.inv_W[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) { ys += v[1 + q]; inv += v[1 + q] * t.inv_W[q]; }
-    inv += (R(1) - ys) * t.inv_W[5];
+    for (int q = 0; q < 5; ++q) inv += v[1 + q] * t.dinv_W[q];
     return (double)fdiv(R(1), inv * v[0]);
   }
 }
@@ -374,25 +395,15 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
     } else {
       // neighbour offsets (relative linear index) and face codes for k = -2..2 per axis
       int off[3][5], code[3][5];
-      {
-        const AxisNb ax = axis_nb(x, a.nx, a.face[0], a.face[1]);
-        const AxisNb ay = axis_nb(y, a.ny, a.face[2], a.face[3]);
+      axis_offsets(x, a.nx, a.face[0], a.face[1], 1, off[0], code[0]);
+      axis_offsets(y, a.ny, a.face[2], a.face[3], a.nx, off[1], code[1]);
+      if (D == 3) {
+        axis_offsets(z, a.nz, a.face[4], a.face[5], nxy, off[2], code[2]);
+      } else {
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-          off[0][k] = ax.idx[k] - x;
-          code[0][k] = ax.code[k];
-          off[1][k] = (ay.idx[k] - y) * a.nx;
-          code[1][k] = ay.code[k];
           off[2][k] = 0;
           code[2][k] = -1;
-        }
-        if (D == 3) {
-          const AxisNb az = axis_nb(z, a.nz, a.face[4], a.face[5]);
-#pragma unroll
-          for (int k = 0; k < 5; ++k) {
-            off[2][k] = (az.idx[k] - z) * nxy;
-            code[2][k] = az.code[k];
-          }
         }
       }
       // status of the axis neighbours at -2, -1, +1, +2
@@ -670,6 +681,8 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             }
             const bool mixed = FULL && NS == 6 && a.mx.on;   // diffusion done before the pull
             if (!mixed) {
+              // differences first: a sum of neighbours minus 2D phi0 would round with a
+              // bias near binade boundaries (values near 1 and 4) in FP32
 #pragma unroll
               for (int q = 0; q < NS; ++q) R_s[q] += cfp * (vp1[q] - phi0[q]) + cfm * (vm1[q] - phi0[q]);
             }
@@ -754,16 +767,12 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
           R_s[0] += heat * invF;
           if (a.thermo) R_s[0] += a.kap * qn * T;         // pressure work
           // Lambda = R_T/T + W sum_k R_k/W_k (N2 by closure: R_N2 = -sum R_k)
-          R ysum = R(0), invW = R(0), acc = R(0), rsum = R(0);
+          R invW = a.th.inv_W[5], acc = R(0);
 #pragma unroll
           for (int q = 0; q < 5; ++q) {
-            ysum += phi0[1 + q];
-            invW += phi0[1 + q] * a.th.inv_W[q];
-            acc += R_s[1 + q] * a.th.inv_W[q];
-            rsum += R_s[1 + q];
+            invW += phi0[1 + q] * a.th.dinv_W[q];
+            acc += R_s[1 + q] * a.th.dinv_W[q];
           }
-          invW += (R(1) - ysum) * a.th.inv_W[5];
-          acc -= rsum * a.th.inv_W[5];
           Lam = R_s[0] * iT + fdiv(acc, invW);
           if (a.thermo) Lam -= qn;                        // div u = Lambda - dln(pi)/dt
         }
@@ -834,7 +843,9 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
         };
         R e[Q];
         R Xi[NS >= 2 ? Q : 1];
-        R Es = R(0), Xs = R(0);
+        R Es = R(0);
+        // sum_i Xi_i = cs2 (rho Lambda + u . grad rho) (the moments of Eq. 2)
+        const R Xs = NS >= 2 ? s * (rho0 * Lam + ugr) : R(0);
         const R half_rcs = fdiv(R(0.5), rho0 * s);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -842,7 +853,6 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
             const R xi = xi_of(i);
             Xi[i] = xi;
             e[i] = r * gh[i] + xi * half_rcs;            // Eq. 13 minus the weights
-            Xs += xi;
           } else {
             e[i] = gh[i];                                // rho = rho_ref, Xi = 0
           }
@@ -893,15 +903,15 @@ __global__ __launch_bounds__(256) void step_kernel(KArgs<typename Prec<PREC>::R>
       }
 
       // ---------------------------------------------------------------- FP64 sums
-      const double rd = (double)rho0;
-      red[0] = rd;
+      // (cell values in the compute precision, accumulated in FP64)
+      red[0] = (double)rho0;
       red[1] = (double)Ph;
-      red[2] = rd * (double)u[0];
-      red[3] = rd * (double)u[1];
-      red[4] = rd * (double)u[2];
-      red[5] = 0.5 * rd * ((double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]);
+      red[2] = (double)(rho0 * u[0]);
+      red[3] = (double)(rho0 * u[1]);
+      red[4] = (double)(rho0 * u[2]);
+      red[5] = (double)(R(0.5) * rho0 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
       red[6] = w_over_T<NS>(a.th, phi0, a.inv_T_ref_d);
-      if constexpr (NS >= 2) red[7] = rd * (double)phi0[1];
+      if constexpr (NS >= 2) red[7] = (double)(rho0 * phi0[1]);
     }
   }
   block_sums(red, a.partials + (size_t)tile * NSUM);
