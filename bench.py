@@ -185,6 +185,20 @@ def traffic_for(name, p, bpc, N):
     return rec.get("bytes_per_launch")
 
 
+def valu_for(name):
+    """VALU issue figures of the step kernel from the committed SQ-counter run, if it was
+    taken on the current kernel sources."""
+    f = os.path.join(ROOT, "profiles", f"valu_{name}.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return {"valu_per_wave": round(rec["valu_per_wave"], 1), "issue_frac": round(rec["valu_issue_frac"], 4),
+            "issue_limit": "one wave instruction per CU per cycle: 256 CUs x 2.4 GHz = 614 G/s"}
+
+
 def precision_errors(steps=2000, n=256):
     """FP32 and FP16-storage runs against the FP64 run of the same seeded HIT field at the
     workload's size (256^3, 2000 steps): velocity relative L2 error and the largest
@@ -331,6 +345,9 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": main_res["bytes_per_cell"] * N}
     extra = {}
+    valu = valu_for(args.workload)
+    if valu is not None:
+        extra["step_kernel_valu"] = valu
     if not args.no_extra:
         for name, prec, k in (("tgv", "fp64", 1000), ("flame2d", "fp64", 400),
                               ("flame2d", "fp32", 400), ("hit", "fp64", 40), ("hit", "fp32", 60),
