@@ -97,6 +97,7 @@ def run_gpu(name, steps, warmup, precision=None, observables=False):
                        torch.from_numpy(s) if s is not None else None)
     del P, u, s
     N = p["nx"] * p["ny"] * p["nz"]
+    n_fluid = N - (int(np.count_nonzero(solid)) if solid is not None else 0)
     extra = {}
     if observables:
         # running statistics at every level and 8 probes along the mid-line
@@ -132,6 +133,7 @@ def run_gpu(name, steps, warmup, precision=None, observables=False):
     torch.cuda.empty_cache()
     return {"workload": name, "desc": desc, "params": p, "cells": N, "steps": steps,
             "ms_per_step": ms / steps, "mlups": N * steps / (ms / 1e3) / 1e6,
+            "fluid_mlups": n_fluid * steps / (ms / 1e3) / 1e6,
             "bytes_per_cell": bpc, "achieved_gbs": achieved, "sums": sums, "observables": extra}
 
 
@@ -183,6 +185,26 @@ def traffic_for(name, p, bpc, N):
     if rec.get("source_hash") != source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=10):
+    """Read + write bandwidth of a plain device-to-device copy of nbytes (torch), timed with
+    HIP events: the practical HBM ceiling beside the 8 TB/s specification."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def valu_for(name):
@@ -344,10 +366,13 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": main_res["bytes_per_cell"] * N}
+    copy_gbs = copy_bandwidth()
     extra = {}
     valu = valu_for(args.workload)
     if valu is not None:
         extra["step_kernel_valu"] = valu
+    extra["hbm_copy_gbs"] = round(copy_gbs, 1)
+    extra["frac_of_copy"] = round(achieved / copy_gbs, 4)
     if not args.no_extra:
         for name, prec, k in (("tgv", "fp64", 1000), ("flame2d", "fp64", 400),
                               ("flame2d", "fp32", 400), ("hit", "fp64", 40), ("hit", "fp32", 60),
@@ -356,7 +381,7 @@ def main():
                               ("chamber2d+observables", "fp64", 400)):
             obs = name.endswith("+observables")
             r = run_gpu(name.split("+")[0], k, 10, prec, observables=obs)
-            extra[f"{name}_{prec}"] = {"mlups": round(r["mlups"], 1),
+            extra[f"{name}_{prec}"] = {"mlups": round(r["mlups"], 1), "fluid_mlups": round(r["fluid_mlups"], 1),
                                        "ms_per_step": round(r["ms_per_step"], 4),
                                        "achieved_gbs": round(r["achieved_gbs"], 1),
                                        "hbm_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
