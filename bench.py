@@ -64,6 +64,15 @@ def workload(name, precision=None):
         p, P, u = L.tgv(128)
         s, solid = None, None
         desc = "Taylor-Green vortex 128^2 D2Q9"
+    elif name == "reacting_box_mixture":
+        p, P, u, s = L.reacting_box()
+        p.update(transport_model="mixture", transport=L.mixture_transport(p["nu_ref"]))
+        desc = "reacting box 192x192x384 D3Q27 FP32 with mixture-averaged transport and c_p(T)"
+        solid = None
+    elif name == "reacting_box_cone":
+        p, P, u, s = L.reacting_box()
+        solid = L.cone_levelset(p["nx"], p["ny"], p["nz"])
+        desc = "reacting box 192x192x384 D3Q27 FP32 with a conical bluff body (curved walls)"
     elif name == "passive_box":
         p, P, u = L.hit(128, seed=11567)
         s = L.passive_field(128)[None]
@@ -91,7 +100,10 @@ def run_gpu(name, steps, warmup, precision=None, observables=False):
     from paper_2207_11567_amd import Solver
     p, P, u, s, solid, desc = workload(name, precision)
     solver = Solver(p, device="cuda:0")
-    if solid is not None:
+    if solid is not None and solid.dtype == np.float64:
+        solver.set_wall_distance(torch.from_numpy(solid))          # signed wall distance
+        solid = solid < 0
+    elif solid is not None:
         solver.set_geometry(torch.from_numpy(solid.astype(np.uint8)))
     solver.init_fields(torch.from_numpy(P), torch.from_numpy(u),
                        torch.from_numpy(s) if s is not None else None)
@@ -322,7 +334,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="reacting_box",
                     choices=["reacting_box", "flame2d", "hit", "tgv", "passive_box", "chamber2d",
-                             "chamber2d_open"])
+                             "chamber2d_open", "reacting_box_mixture", "reacting_box_cone"])
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "fp16s"])
     ap.add_argument("--observables", action="store_true",
                     help="sample running statistics and 8 probes at every step of the main workload")
@@ -378,7 +390,8 @@ def main():
                               ("flame2d", "fp32", 400), ("hit", "fp64", 40), ("hit", "fp32", 60),
                               ("hit", "fp16s", 60), ("passive_box", "fp32", 100),
                               ("chamber2d", "fp64", 400), ("chamber2d_open", "fp64", 400),
-                              ("chamber2d+observables", "fp64", 400)):
+                              ("chamber2d+observables", "fp64", 400), ("reacting_box_mixture", "fp32", 40),
+                              ("reacting_box_cone", "fp32", 40)):
             obs = name.endswith("+observables")
             r = run_gpu(name.split("+")[0], k, 10, prec, observables=obs)
             extra[f"{name}_{prec}"] = {"mlups": round(r["mlups"], 1), "fluid_mlups": round(r["fluid_mlups"], 1),

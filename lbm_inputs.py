@@ -226,6 +226,26 @@ def chamber2d(nx=2500, ny=500, Tu=300.0, Tb=2000.0, F=4.0, FD=0.03, cs_smag=0.17
     return params, P, u, scal, mask
 
 
+def cone_levelset(nx, ny, nz, base=0.2, height=0.16, z0=0.04):
+    """Signed distance (cells, positive in the fluid) to a solid cone on the axis of an
+    nx x ny x nz box, pointing downstream (+z): base radius base*min(nx, ny) at z0*nz,
+    apex height*nz further on; a stand-in for the burner's conical bluff body.  Inside
+    the cone the distance is the negative distance to its mantle or base."""
+    R = base * min(nx, ny)
+    H = height * nz
+    zb = z0 * nz
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    r = np.hypot(x - nx / 2.0, y - ny / 2.0)
+    h = z - zb                                     # height above the base plane
+    L = math.hypot(R, H)
+    # distance to the (infinite) mantle line in the (r, h) half-plane, signed
+    d_mantle = (r * H + h * R - R * H) / L         # > 0 outside, < 0 inside
+    inside = (h >= 0) & (h <= H) & (d_mantle < 0)
+    d_base = -h                                    # > 0 below the base plane
+    outside = np.maximum(d_mantle, d_base)         # convex solid: max of the half-spaces
+    return np.where(inside, np.maximum(d_mantle, np.maximum(d_base, h - H)), outside)
+
+
 def reacting_box(nx=192, ny=192, nz=384, u_in=0.1, noise=0.05, phi=0.83, T_in=320.0,
                  T_b=1950.0, F=5.0, nu=5e-4, cs_smag=0.17, seed=2207, chem=None):
     """3-D box, periodic in x and y, inlet at z = 0 and outlet at z = nz-1, fresh CH4/air

@@ -21,7 +21,9 @@ pytestmark = pytest.mark.gpu
 def _gpu_run(params, P, u, scal, mask, steps):
     from paper_2207_11567_amd import Solver
     s = Solver(params)
-    if mask is not None:
+    if mask is not None and mask.dtype == np.float64:
+        s.set_wall_distance(torch.from_numpy(mask))         # signed wall distance
+    elif mask is not None:
         s.set_geometry(torch.from_numpy(mask))
     s.init_fields(torch.from_numpy(P), torch.from_numpy(u),
                   torch.from_numpy(scal) if scal is not None else None)
@@ -71,13 +73,17 @@ def _window(params, full, mask, origin, size):
     sel = np.ix_(idx[2], idx[1], idx[0])
     wp = dict(params, nx=len(idx[0]), ny=len(idx[1]), nz=len(idx[2]), face_bc=wf,
               noise_origin=(int(idx[0][0]), int(idx[1][0]), int(idx[2][0])))
+    phi = None
+    if mask is not None and mask.dtype == np.float64:
+        phi = torch.from_numpy(np.ascontiguousarray(mask[sel]))
+        mask = mask < 0
     solid = None if mask is None else torch.from_numpy(mask[sel].astype(bool))
     # the window's inputs: equilibrium from the FP64 fields, then stored (scalars and
     # populations rounded to the storage precision as the GPU stores them)
     sc_w = None if scal is None else np.ascontiguousarray(scal[(slice(None),) + sel])
     st = OS.init_state(wp, torch.from_numpy(np.ascontiguousarray(P[sel])),
                        torch.from_numpy(np.ascontiguousarray(u[(slice(None),) + sel])),
-                       None if sc_w is None else torch.from_numpy(sc_w), solid)
+                       None if sc_w is None else torch.from_numpy(sc_w), solid, phi)
     if sc_w is not None:
         st["scal"] = torch.from_numpy(sc_w.astype(SCAL_NP[params["precision"]]).astype(np.float64))
     if params["precision"] != "fp64":
@@ -158,3 +164,14 @@ def test_reacting_box_mixture_transport_full_size_windows():
     full = _gpu_run(params, P, u, scal, None, 2)
     for origin, size in (((50, 60, 0), (12, 12, 10)), ((90, 100, 184), (12, 12, 16))):
         _check(_window(params, full, None, origin, size), "fp32", 2)
+
+
+def test_reacting_box_cone_curved_walls_full_size_windows():
+    """The reacting box with a conical bluff body given by its signed distance (curved
+    walls, FULL kernel instance): windows at the cone's base edge and its apex."""
+    params, P, u, scal = L.reacting_box()
+    phi = L.cone_levelset(params["nx"], params["ny"], params["nz"])
+    full = _gpu_run(params, P, u, scal, phi, 2)
+    for origin, size in (((52, 90, 12), (14, 12, 10)),        # base rim
+                         ((90, 90, 70), (12, 12, 12))):       # apex
+        _check(_window(params, full, phi, origin, size), "fp32", 2)
