@@ -18,8 +18,17 @@ Readings taken here (they are the specification of this operator):
   back after collision.  m0 and the first moment are not relaxed.
 * Equilibria: off-diagonal and deviatoric second-order cumulants 0, their trace D cs2;
   every cumulant of order >= 3 is 0.  Rates: omega_s for shear/deviatoric, omega_bulk for
-  the trace, omega_high for every order >= 3 (Geier's optional Galilean corrections and
-  fourth-order parameterisation are not used).
+  the trace, omega_high for every order >= 3 (Geier's fourth-order parameterisation is
+  not used).
+* Optional Galilean correction (Geier et al. 2015, switched on by
+  params["galilean"]): on the velocity sets used here c^3 = c, so the equilibrium third
+  diagonal moment of f~ is u_a instead of u_a + u_a^3 and the Chapman-Enskog stress
+  carries an error (1/omega - 1/2) d_a(u_a^3) ~ (1/omega - 1/2) 3 u_a^2 d_a u_a on each
+  diagonal (f~ has density one).  A post-collision source S_aa = -3 (1 - omega/2) u_a^2
+  d_a u_a cancels it to that order: the deviatoric differences take it with omega_s, the
+  trace with omega_bulk.  The diagonal velocity derivatives come from the pre-collision
+  non-equilibrium second cumulants through the same balance:
+  d_a u_a = -(omega_s / (2 cs2)) (C_aa - tr/D) - (omega_bulk / (2 cs2 D)) (tr - D cs2).
 * Sub-grid model (Smagorinsky, Hou et al. closed form): with the non-equilibrium second
   moment Pi = kappa_2(f~) - cs2 I of the pre-collision state and Qbar = sqrt(2 Pi:Pi),
   tau = (tau0 + sqrt(tau0^2 + 2 Cs^2 Qbar / cs2^2)) / 2, filter width dr = 1.
@@ -144,14 +153,33 @@ def smagorinsky_omega(lat, kappa, nu, cs_smag):
     return 1.0 / tau
 
 
-def relax(lat, C, omega_s, omega_bulk, omega_high):
-    """Relaxation (Eq. 9 as read): K* = (I - W) K + W K_eq, cumulant by cumulant."""
+def diagonal_strain(lat, C, omega_s, omega_bulk):
+    """d_a u_a (a = 0..D-1) from the pre-collision second cumulants of the density-one
+    distribution: C_aa - tr/D = -(2 cs2/omega_s) (d_a u_a - div u / D) and
+    tr - D cs2 = -(2 cs2/omega_bulk) div u (first-order Chapman-Enskog balance)."""
+    D = lat.D
+    diag = [C[_unit(D, a, a)] for a in range(D)]
+    trace = sum(diag)
+    div = -omega_bulk / (2.0 * CS2) * (trace - D * CS2)
+    return [-omega_s / (2.0 * CS2) * (diag[a] - trace / D) + div / D for a in range(D)]
+
+
+def relax(lat, C, omega_s, omega_bulk, omega_high, u=None):
+    """Relaxation (Eq. 9 as read): K* = (I - W) K + W K_eq, cumulant by cumulant; with
+    the velocity u given, the diagonal second cumulants also take Geier's Galilean
+    correction source S_aa = -3 (1 - omega/2) u_a^2 d_a u_a (omega_s on the deviatoric
+    differences, omega_bulk on the trace)."""
     D = lat.D
     Cs = {}
     diag = [_unit(D, a, a) for a in range(D)]
     trace = sum(C[e] for e in diag)
     trace_s = trace + omega_bulk * (D * CS2 - trace)
     devs = [(1.0 - omega_s) * (C[diag[0]] - C[diag[a]]) for a in range(1, D)]
+    if u is not None:
+        dd = diagonal_strain(lat, C, omega_s, omega_bulk)
+        S = [-3.0 * u[a] * u[a] * dd[a] for a in range(D)]
+        trace_s = trace_s + (1.0 - 0.5 * omega_bulk) * sum(S)
+        devs = [devs[a - 1] + (1.0 - 0.5 * omega_s) * (S[0] - S[a]) for a in range(1, D)]
     # c_aa* from trace* and the deviators (c_xx - c_aa)*
     cxx = (trace_s + sum(devs)) / D
     Cs[diag[0]] = cxx
@@ -181,12 +209,12 @@ def central_to_raw(lat, kappa, u):
     return m
 
 
-def cumulant_collide(lat, f_prime, u, nu, cs_smag, omega_bulk, omega_high, omega_s=None):
+def cumulant_collide(lat, f_prime, u, nu, cs_smag, omega_bulk, omega_high, omega_s=None, galilean=False):
     """Post-collision pre-conditioned populations f'* (Eq. 9 as read).
 
     f_prime: (Q, *grid); u: (D, *grid) the velocity of Eq. 7b; nu: molecular kinematic
     viscosity (scalar or *grid); omega_s, if given, replaces the shear rate of Eq. 12 and
-    the sub-grid model.  Returns (f'*, omega_s)."""
+    the sub-grid model; galilean adds the Galilean correction.  Returns (f'*, omega_s)."""
     nd = f_prime.ndim - 1
     w = lat.w.reshape((-1,) + (1,) * nd)
     m0 = f_prime.sum(0)
@@ -195,7 +223,7 @@ def cumulant_collide(lat, f_prime, u, nu, cs_smag, omega_bulk, omega_high, omega
     if omega_s is None:
         omega_s = smagorinsky_omega(lat, kappa, nu, cs_smag)
     C = moments_to_cumulants(kappa)
-    Cs = relax(lat, C, omega_s, omega_bulk, omega_high)
+    Cs = relax(lat, C, omega_s, omega_bulk, omega_high, u if galilean else None)
     kappa_s = cumulants_to_moments(Cs, m0)
     for e in lat.exps:           # orders 0 and 1 pass through unrelaxed
         if sum(e) < 2:

@@ -179,7 +179,8 @@ def step(params, state):
     nu = scalars.viscosity(params, rho, state["scal"][0] if state["scal"].shape[0] else None)
     if params["collision"] == "cumulant":
         fps, _ = cumulant.cumulant_collide(lat, fp, u, nu, params["cs_smag"],
-                                           params["omega_bulk"], params["omega_high"])
+                                           params["omega_bulk"], params["omega_high"],
+                                           galilean=bool(params.get("galilean", 0)))
     else:
         w = lat.w.reshape((-1,) + (1,) * 3)
         f_t = fp - w * (fp.sum(0) - 1.0)
