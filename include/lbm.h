@@ -109,7 +109,17 @@ typedef struct {
                               (CH4, O2, CO, CO2, H2O, N2) in the order (0,1) (0,2) .. (4,5)
                               [0..14], c_p,k = a_k + b_k T: a [15..20], b [21..26] (J/kg/K),
                               exponents s_mu [27], s_D [28] */
+  int32_t galilean;        /* 0 | 1: Galilean correction of the cumulant collision (Geier
+                              et al. 2015, whose operator Sec. 2.2 applies), see below;
+                              requires LBM_CUMULANT */
 } lbm_params;
+
+/* Galilean correction: on D2Q9 and D3Q27 c^3 = c, so the equilibrium third diagonal moment
+ * lacks u_a^3 and the viscous stress picks up (1/omega - 1/2) 3 u_a^2 d_a u_a on each
+ * diagonal.  With galilean = 1 the collision estimates d_a u_a from the pre-collision
+ * second cumulants (deviatoric part at the shear rate, trace at omega_bulk) and adds
+ * -3 (1 - omega/2) u_a^2 d_a u_a to the post-collision diagonal (shear rate on the
+ * deviatoric differences, omega_bulk on the trace).  Not covered by the adjoint. */
 
 /* Mixture-averaged transport (the paper evaluates its thermodynamic and transport
  * properties with mixture-averaged approximations, Sec. 2.3; the module and data are

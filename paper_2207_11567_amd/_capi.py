@@ -34,7 +34,8 @@ class LbmParams(ctypes.Structure):
                 ("outlet_P", c_double), ("inlet_T", c_double), ("inlet_Y", c_double * 8),
                 ("weno_scale", c_double * 8), ("chem", c_double * 32), ("seed", c_uint64),
                 ("pth_mode", c_int32), ("gamma", c_double),
-                ("transport_model", c_int32), ("transport", c_double * 32)]
+                ("transport_model", c_int32), ("transport", c_double * 32),
+                ("galilean", c_int32)]
 
 
 def make_params(d):
@@ -65,6 +66,7 @@ def make_params(d):
     p.transport_model = TRANSPORT[d.get("transport_model", "simple")]
     for i, v in enumerate(list(d.get("transport", [0.0] * 32))[:32]):
         p.transport[i] = float(v)
+    p.galilean = int(d.get("galilean", 0))
     return p
 
 

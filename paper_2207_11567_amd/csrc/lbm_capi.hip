@@ -72,6 +72,8 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   if (p->lattice == LBM_D2Q9 && p->nz != 1) return fail("D2Q9 requires nz == 1");
   if (p->precision < 0 || p->precision > 2) return fail("precision must be LBM_FP64, LBM_FP32 or LBM_FP16S");
   if (p->collision != LBM_CUMULANT && p->collision != LBM_BGK) return fail("unknown collision operator");
+  if (p->galilean != 0 && p->galilean != 1) return fail("galilean must be 0 or 1");
+  if (p->galilean && p->collision != LBM_CUMULANT) return fail("the Galilean correction belongs to the cumulant collision");
   const int NS = n_scalars(p->physics);
   if (NS < 0) return fail("unknown physics");
   if (p->visc_law != LBM_VISC_CONST_NU && p->visc_law != LBM_VISC_CONST_MU) return fail("unknown visc_law");
@@ -204,6 +206,7 @@ static StepArgs make_args(const lbm_solver *s) {
   if (s->D == 2) a.face[4] = a.face[5] = -1;
   a.step = s->step;
   a.collision = p.collision;
+  a.gal = p.galilean;
   a.remap = 1;
   a.band_rows = 0;
   if (p.nx % 64 == 0 && p.ny % 4 == 0)
@@ -612,6 +615,7 @@ static lbm_status adjoint_supported(lbm_solver *s) {
   else if (p.physics != LBM_ISOTHERMAL && p.physics != LBM_PASSIVE) why = "the adjoint covers isothermal and passive-temperature flows";
   else if (p.collision != LBM_CUMULANT) why = "the adjoint covers the cumulant collision";
   else if (p.omega_high != 1.0) why = "the adjoint needs omega_high == 1";
+  else if (p.galilean) why = "the adjoint covers the collision without the Galilean correction";
   else if (p.precision == LBM_FP16S) why = "the adjoint runs in FP64 or FP32";
   else if (s->has_geom) why = "the adjoint covers domains without solid cells";
   else if (s->closed) why = "the adjoint covers a constant thermodynamic pressure";

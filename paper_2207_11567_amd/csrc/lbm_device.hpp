@@ -87,10 +87,19 @@ template <class R> __device__ __forceinline__ void inv3(R &k0, R &k1, R &k2, R u
 // and the transformed deviation part kappa^d; second-order diagonal moments are carried
 // as A = kappa_aa - cs2 so that no O(1) quantity is ever subtracted from another.
 // Returns the shear rate used (Smagorinsky closed form on tau).
+//
+// Galilean correction (Geier et al. 2015): on these velocity sets c^3 = c, so the
+// equilibrium third diagonal moment misses u_a^3 and the Chapman-Enskog stress carries
+// (1/omega - 1/2) 3 u_a^2 d_a u_a on each diagonal.  With d_a u_a estimated from the
+// pre-collision non-equilibrium second cumulants (A, B, C: deviatoric part at the shear
+// rate, trace at the bulk rate), the post-collision diagonal receives the cancelling
+// source -3 (1 - omega/2) u_a^2 d_a u_a, omega being the shear rate for the deviatoric
+// differences and the bulk rate for the trace.
 template <class R> struct Rates {
   R tau0;      // nu/cs2 + 1/2 (Eq. 12 read as relaxation time)
   R smag18;    // 18 Cs^2 = 2 Cs^2 / cs2^2
   R wb, wh;    // bulk and higher-order rates
+  bool gal;    // Galilean correction of the diagonal second-order cumulants
 };
 
 template <class R>
@@ -119,8 +128,15 @@ __device__ __forceinline__ R collide_d2q9(R (&d)[9], R ux, R uy, const Rates<R> 
   const R c22 = d[8] - s * (d[2] + d[6]) + ux2 * uy2 - A * B - R(2) * k11 * k11;
   const R om = shear_rate(rt, A * A + B * B + R(2) * k11 * k11);
   // relax
-  const R Dxy = (R(1) - om) * (A - B);
-  const R Tr = (R(1) - rt.wb) * (A + B);
+  R Dxy = (R(1) - om) * (A - B);
+  R Tr = (R(1) - rt.wb) * (A + B);
+  if (rt.gal) {
+    // d_x u, d_y v = -(3 om / 4) (A - B) -+ ... - (3 wb / 4) (A + B)
+    const R dv = R(0.75) * om * (A - B), tv = R(0.75) * rt.wb * (A + B);
+    const R Sx = R(-3) * ux2 * (-dv - tv), Sy = R(-3) * uy2 * (dv - tv);
+    Dxy += (R(1) - R(0.5) * om) * (Sx - Sy);
+    Tr += (R(1) - R(0.5) * rt.wb) * (Sx + Sy);
+  }
   const R As = R(0.5) * (Tr + Dxy), Bs = R(0.5) * (Tr - Dxy);
   const R k11s = (R(1) - om) * k11;
   const R h = R(1) - rt.wh;
@@ -201,8 +217,19 @@ __device__ __forceinline__ R collide_d3q27(R (&d)[27], R ux, R uy, R uz, const R
   const R om = shear_rate(rt, A * A + B * B + C * C + R(2) * (k110 * k110 + k101 * k101 + k011 * k011));
   // relaxation towards the cumulant equilibria
   const R o1 = R(1) - om, h = HIGH1 ? R(0) : R(1) - rt.wh;
-  const R Dxy = o1 * (A - B), Dxz = o1 * (A - C);
-  const R Tr = (R(1) - rt.wb) * (A + B + C);
+  R Dxy = o1 * (A - B), Dxz = o1 * (A - C);
+  R Tr = (R(1) - rt.wb) * (A + B + C);
+  if (rt.gal) {
+    // d_a u_a = -(om / 2) (3 A_a - tr) - (wb / 2) tr, tr = A + B + C
+    const R tr = A + B + C, ho = R(0.5) * om, tb = R(0.5) * rt.wb * tr;
+    const R Sx = R(-3) * ux2 * (-ho * (R(3) * A - tr) - tb);
+    const R Sy = R(-3) * uy2 * (-ho * (R(3) * B - tr) - tb);
+    const R Sz = R(-3) * uz2 * (-ho * (R(3) * C - tr) - tb);
+    const R gs = R(1) - ho;
+    Dxy += gs * (Sx - Sy);
+    Dxz += gs * (Sx - Sz);
+    Tr += (R(1) - R(0.5) * rt.wb) * (Sx + Sy + Sz);
+  }
   const R As = (Tr + Dxy + Dxz) * R(1.0 / 3.0);
   const R Bs = As - Dxy, Cs = As - Dxz;
   const R q110 = o1 * k110, q101 = o1 * k101, q011 = o1 * k011;

@@ -38,6 +38,8 @@ def test_exports_every_declared_symbol():
     ({"pth_mode": "closed", "face_bc": ["inlet", "outlet", "wall", "wall", "periodic", "periodic"]},
      "closed domain"),
     ({"pth_mode": "closed", "gamma": 1.0}, "gamma"),
+    ({"galilean": 2}, "galilean"),
+    ({"galilean": 1, "collision": "bgk"}, "cumulant"),
 ])
 def test_validation_rejects(change, needle):
     C, lib = _lib()
