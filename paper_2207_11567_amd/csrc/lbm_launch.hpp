@@ -32,19 +32,52 @@ hipError_t launch_surface(int Q, int prec, const StepArgs &a, int nblocks, hipSt
 hipError_t launch_statistics(const double *acc, int D, long long N, long long k, double P0, double *mean, double *rms,
                              hipStream_t st);
 
+// Collision instance for the parameters: BGK, or the cumulant operator with every order
+// >= 3 at rate one (decided in the compute precision, as the kernel would), or general.
+template <int Q, int PREC>
+int collision_instance(const StepArgs &a) {
+  using R = typename Prec<PREC>::R;
+  if (a.collision != 0) return COLL_BGK;
+  return (Q == 27 && (R)a.wh != R(1)) ? COLL_CUM : COLL_CUM1;
+}
+
+template <int Q, int PREC, int NS, bool FULL>
+hipError_t launch_step(const StepArgs &a, int nblocks, hipStream_t st) {
+  using R = typename Prec<PREC>::R;
+  switch (collision_instance<Q, PREC>(a)) {
+    case COLL_CUM1:
+      hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, FULL, COLL_CUM1>), dim3(nblocks), dim3(256), 0, st,
+                         to_kargs<R>(a));
+      break;
+    case COLL_CUM:
+      if constexpr (Q == 27)
+        hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, FULL, COLL_CUM>), dim3(nblocks), dim3(256), 0, st,
+                           to_kargs<R>(a));
+      else
+        return hipErrorInvalidValue;
+      break;
+    default:
+      hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, FULL, COLL_BGK>), dim3(nblocks), dim3(256), 0, st,
+                         to_kargs<R>(a));
+  }
+  return hipGetLastError();
+}
+
 template <int Q, int PREC, int NS>
 hipError_t launch_one(int kind, const StepArgs &a, int nblocks, hipStream_t st, const double *Ph,
                       const double *u, const double *scal) {
   using R = typename Prec<PREC>::R;
   const bool full = a.lvl || a.stats || a.probe_out || a.mix;
   if (kind == LAUNCH_STEP && full)
-    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, true>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
+    return launch_step<Q, PREC, NS, true>(a, nblocks, st);
   else if (kind == LAUNCH_STEP)
-    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, false>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
-  else if (kind == LAUNCH_EXTRACT && full)
-    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, true>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
+    return launch_step<Q, PREC, NS, false>(a, nblocks, st);
+  else if (kind == LAUNCH_EXTRACT && full)   // no collision on the extract path
+    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, true, COLL_CUM1>), dim3(nblocks), dim3(256), 0, st,
+                       to_kargs<R>(a));
   else if (kind == LAUNCH_EXTRACT)
-    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, false>), dim3(nblocks), dim3(256), 0, st, to_kargs<R>(a));
+    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, false, COLL_CUM1>), dim3(nblocks), dim3(256), 0, st,
+                       to_kargs<R>(a));
   else
     hipLaunchKernelGGL((init_kernel<Q, PREC, NS>), dim3(nblocks), dim3(256), 0, st, to_kargs<double>(a), Ph,
                        u, scal);
