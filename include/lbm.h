@@ -187,7 +187,9 @@ lbm_status lbm_fields(lbm_solver *s, double *P_h, double *rho, double *u, double
 lbm_status lbm_step_from(lbm_solver *s, const void *pops_in, const void *scal_in,
                          void *pops_out, void *scal_out, int64_t step);
 
-/* The 8 sums formed by the last lbm_step (at the level of its last step).  Synchronises. */
+/* The 8 sums formed by the last lbm_step or lbm_step_from (at the level of its last step);
+ * lbm_fields, lbm_flame_surface and lbm_objective keep their block records apart and
+ * leave them untouched.  Synchronises. */
 lbm_status lbm_step_sums(lbm_solver *s, double *sums_host);
 
 /* Raw state copies (device-to-device, storage format): pops [Q][N], scal [S][N].

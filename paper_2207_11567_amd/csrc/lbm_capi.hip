@@ -25,7 +25,8 @@ struct lbm_solver {
   int Q, NS, D, prec, nblocks;
   int *flag;
   double *sums;
-  double *partials;
+  double *partials;   // [nblocks][NSUM]: block records of lbm_step
+  double *aux;        // block records of field extraction, flame surface and objective
   double *stage;
   double *thermo;     // (pi, q, K) of the closed-domain thermodynamic pressure
   bool closed;
@@ -136,6 +137,7 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   L->NS = NS;
   L->D = Dm;
   L->nblocks = (int)((N + 255) / 256);
+  const int nrec = 2 * L->nblocks;         // step records, then those of the other reductions
   L->pop_bytes = (size_t)Q * N * pop_elem(p->precision);
   L->scal_bytes = (size_t)NS * N * scal_elem(p->precision);
   L->off_flag = 0;
@@ -143,7 +145,7 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   L->off_thermo = 192;                    // 3 doubles
   L->off_stage = 256;
   L->off_partials = L->off_stage + 256 * NSUM * sizeof(double);
-  L->off_geom = align256(L->off_partials + (size_t)L->nblocks * NSUM * sizeof(double));
+  L->off_geom = align256(L->off_partials + (size_t)nrec * NSUM * sizeof(double));
   L->work_bytes = align256(L->off_geom + (size_t)N * (Q == 9 ? 4 : 8));
   return LBM_OK;
 }
@@ -305,6 +307,7 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
   s->flag = (int *)(s->work + L.off_flag);
   s->sums = (double *)(s->work + L.off_sums);
   s->partials = (double *)(s->work + L.off_partials);
+  s->aux = s->partials + (size_t)L.nblocks * NSUM;
   s->stage = (double *)(s->work + L.off_stage);
   s->thermo = (double *)(s->work + L.off_thermo);
   s->closed = p->pth_mode == LBM_PTH_CLOSED;
@@ -466,9 +469,16 @@ lbm_status lbm_fields(lbm_solver *s, double *P_h, double *rho, double *u, double
   a.f_rho = rho;
   a.f_u = u;
   a.f_scal = scal;
+  a.partials = s->aux;                  // the step's own records stay for lbm_step_sums
   hipError_t e = launch(s, LAUNCH_EXTRACT, a);
   if (e != hipSuccess) return hip_fail(s, e, "field extraction kernel");
-  return lbm_step_sums(s, sums_host);
+  e = launch_finalize(s->aux, s->nblocks, s->stage, s->sums, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "finalize kernel");
+  if (sums_host) {
+    e = hipMemcpyAsync(sums_host, s->sums, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "copying sums");
+  }
+  return check_flag(s);
 }
 
 lbm_status lbm_get_state(lbm_solver *s, void *pops_dst, void *scal_dst, int64_t *step) {
@@ -573,8 +583,9 @@ lbm_status lbm_flame_surface(lbm_solver *s, double T_u, double T_b, double *surf
   }
   StepArgs a = make_args(s);
   a.scal_in = s->scal[s->cur];
+  a.partials = s->aux;
   hipError_t e = launch_surface(s->Q, s->prec, a, s->nblocks, s->stream, T_u, T_b);
-  if (e == hipSuccess) e = launch_finalize(s->partials, s->nblocks, s->stage, s->sums, s->stream);
+  if (e == hipSuccess) e = launch_finalize(s->aux, s->nblocks, s->stage, s->sums, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(surface_host, s->sums, sizeof(double), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "flame surface");
@@ -673,11 +684,12 @@ lbm_status lbm_objective(lbm_solver *s, const void *state_pops, const void *stat
   StepArgs a = make_args(s);
   a.pop_in = state_pops;
   a.scal_in = state_scal;
+  a.partials = s->aux;
   hipError_t e = launch_adjoint(s->prec, s->NS, 1, a, s->nblocks, s->stream, nullptr, nullptr, nullptr, nullptr,
                                 nullptr, 0.0, nullptr, nullptr);
   if (e != hipSuccess) return hip_fail(s, e, "objective sums");
   double sums[8];
-  e = launch_finalize(s->partials, s->nblocks, s->stage, s->sums, s->stream);
+  e = launch_finalize(s->aux, s->nblocks, s->stage, s->sums, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(sums, s->sums, sizeof sums, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "objective sums");

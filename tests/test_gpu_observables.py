@@ -138,3 +138,20 @@ def test_chamber_initial_flame_surface_full_size():
     exp = DG.flame_surface(p, grid, torch.from_numpy(scal[0]), 300.0, 2000.0)
     assert abs(A / exp - 1) < 1e-12
     assert abs(A / (math.pi * 100.0) - 1) < 1e-2
+
+
+def test_step_sums_survive_other_reductions():
+    """The sums of the last step are not overwritten by the flame-surface, field-extraction
+    or other block reductions that run in between."""
+    p, P, u, scal, solid = _flame_box("fp64")
+    s = make_solver(p)
+    s.set_geometry(torch.from_numpy(solid.astype(np.uint8)))
+    s.init_fields(torch.from_numpy(P), torch.from_numpy(u), torch.from_numpy(scal))
+    s.step(4)
+    before = s.step_sums()
+    s.flame_surface(300.0, 2000.0)
+    f = s.fields()
+    after = s.step_sums()
+    s.close()
+    assert before == after
+    assert f["sums"] != before                    # the extraction sums the next level
