@@ -233,17 +233,17 @@ def valu_for(name):
             "issue_limit": "one wave instruction per CU per cycle: 256 CUs x 2.4 GHz = 614 G/s"}
 
 
-def precision_errors(steps=2000, n=256):
-    """FP32 and FP16-storage runs against the FP64 run of the same seeded HIT field at the
-    workload's size (256^3, 2000 steps): velocity relative L2 error and the largest
-    shell-averaged energy-spectrum relative error over 1 <= k < n/2."""
+def precision_errors(steps=2000, n=256, rsteps=200):
+    """FP32 and FP16-storage runs against the FP64 run of the same seeded input: the HIT
+    field at the workload's size (256^3, 2000 steps; velocity and P_h errors, shell-averaged
+    energy spectrum) and the reacting box (192x192x384, 200 steps; velocity, P_h, T and the
+    five transported species).  Field errors are relative L2 norms of the difference over
+    the norm of the FP64 field's deviation from its mean; the FP64 path itself matches the
+    oracle to 1e-11.  Also the step time of each precision (HIP events) and its speedup over
+    FP64."""
     import torch
 
     from paper_2207_11567_amd import Solver
-    p0, P, u = L.hit(n)
-    out = {}
-    spectra = {}
-    ref_u = None
 
     def spectrum(v):
         e = np.zeros(n // 2 - 1)
@@ -255,26 +255,63 @@ def precision_errors(steps=2000, n=256):
             e += np.bincount(shells, (0.5 * np.abs(vk) ** 2).ravel(), minlength=n)[1:n // 2]
         return e
 
-    for prec in ("fp64", "fp32", "fp16s"):
-        p = dict(p0, precision=prec)
+    def rel(a, ref):
+        dev = ref - ref.mean(axis=tuple(range(1, ref.ndim)), keepdims=True)
+        return float(np.sqrt(((a - ref) ** 2).sum() / (dev ** 2).sum()))
+
+    def run(p, P, u, sc, k):
         s = Solver(p, device="cuda:0")
-        s.init_fields(torch.from_numpy(P), torch.from_numpy(u))
-        s.step(steps)
-        uf = s.fields()["u"].cpu().numpy()
+        s.init_fields(torch.from_numpy(P), torch.from_numpy(u), torch.from_numpy(sc) if sc is not None else None)
+        s.step(10)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(k - 10)
+        e1.record(s.stream)
+        f = s.fields()
+        ms = e0.elapsed_time(e1) / (k - 10)
+        out = {"u": f["u"].cpu().numpy(), "P_h": f["P_h"].cpu().numpy()[None], "scal": f["scal"].cpu().numpy()}
         s.close()
         torch.cuda.empty_cache()
-        spectra[prec] = spectrum(uf)
+        return out, ms
+
+    res = {"hit": {}, "reacting_box": {}}
+    speed = {"hit": {}, "reacting_box": {}}
+    p0, P, u = L.hit(n)
+    ref = None
+    spectra = {}
+    for prec in ("fp64", "fp32", "fp16s"):
+        f, ms = run(dict(p0, precision=prec), P, u, None, steps)
+        speed["hit"][prec] = ms
+        spectra[prec] = spectrum(f["u"])
         if prec == "fp64":
-            ref_u = uf
-        else:
-            d = uf - ref_u
-            out[prec] = {"u_rel_l2": float(np.sqrt((d ** 2).sum() / (ref_u ** 2).sum()))}
-    for prec in ("fp32", "fp16s"):
-        rel = np.abs(spectra[prec] - spectra["fp64"]) / spectra["fp64"]
-        out[prec]["spectrum_max_rel_err"] = float(rel.max())
-        out[prec]["spectrum_rel_err_k_le_16"] = float(rel[:16].max())
-        out[prec]["case"] = f"HIT {n}^3 D3Q27, {steps} steps, Smagorinsky 0.17"
-    return out
+            ref = f
+            continue
+        r = {"u_rel_l2": rel(f["u"], ref["u"]), "P_h_rel_l2": rel(f["P_h"], ref["P_h"])}
+        sp = np.abs(spectra[prec] - spectra["fp64"]) / spectra["fp64"]
+        r["spectrum_max_rel_err"] = float(sp.max())
+        r["spectrum_rel_err_k_le_16"] = float(sp[:16].max())
+        r["case"] = f"HIT {n}^3 D3Q27, {steps} steps, Smagorinsky 0.17"
+        res["hit"][prec] = r
+    del ref, spectra
+    p0, P, u, sc = L.reacting_box()
+    names = ["T", "CH4", "O2", "CO", "CO2", "H2O"]
+    ref = None
+    for prec in ("fp64", "fp32", "fp16s"):
+        f, ms = run(dict(p0, precision=prec), P, u, sc, rsteps)
+        speed["reacting_box"][prec] = ms
+        if prec == "fp64":
+            ref = f
+            continue
+        r = {"u_rel_l2": rel(f["u"], ref["u"]), "P_h_rel_l2": rel(f["P_h"], ref["P_h"])}
+        for k, nm in enumerate(names):
+            r[f"{nm}_rel_l2"] = rel(f["scal"][k:k + 1], ref["scal"][k:k + 1])
+        r["case"] = f"reacting box 192x192x384 D3Q27 two-step, {rsteps} steps"
+        res["reacting_box"][prec] = r
+    sp = {w: {"ms_per_step": {k: round(v, 4) for k, v in t.items()},
+              "speedup_over_fp64": {k: round(t["fp64"] / v, 3) for k, v in t.items() if k != "fp64"}}
+          for w, t in speed.items()}
+    return res, sp
 
 
 def differentiation(nsteps=2000, seg=100, n=128):
@@ -402,7 +439,8 @@ def main():
             if r["observables"]:
                 extra[f"{name}_{prec}"]["observables"] = {k2: round(v, 6) for k2, v in r["observables"].items()}
             print(f"# {name} {prec}: {r['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
-        extra["precision_error_vs_fp64"] = precision_errors()
+        extra["precision_error_vs_fp64"], extra["precision_speed"] = precision_errors()
+        print(f"# precision: {extra['precision_speed']}", file=sys.stderr, flush=True)
         extra["differentiation"] = differentiation()
         print(f"# differentiation: {extra['differentiation']}", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(args.workload)

@@ -64,7 +64,13 @@ def mean_W(Y):
     return 1.0 / sum(y / w for y, w in zip(Y, W_SPECIES))
 
 
-def two_step_chem(B1=2.0e4, Ta1=15000.0, B2=2.0e3, Ta2=6000.0, cp=1400.0, phi=0.83):
+def two_step_chem(B1=2.0e4, Ta1=15000.0, B2=1.0e2, Ta2=6000.0, cp=1400.0, phi=0.83):
+    """Placeholder 2-step CH4/air constants (lattice units; the paper's calibrated set is not
+    available).  The scalars advance by explicit Euler, so the CO oxidation rate per step,
+    lambda_CO = (B2/F) exp(-Ta2/T) (rho Y_O2/W_O2)^(1/2), must stay below one for a monotone
+    update: B2 = 100 gives about 0.4 in the burnt gas of the reacting box (F = 5); B2 = 2000
+    gave about 8, an unstable update whose CO swung negative and turned the burnt region
+    chaotic."""
     yf, yo, yn = fresh_ch4_air(phi)
     W_ref = mean_W([yf, yo, 0.0, 0.0, 0.0, yn])
     return [B1, Ta1, B2, Ta2, cp] + W_SPECIES + H_SPECIES + [W_ref]

@@ -8,6 +8,7 @@ import torch
 
 import lbm_inputs as L
 from oracle import noise, scalars
+from oracle.grid import Grid
 from oracle import step as S
 from oracle.lattice import CS2
 
@@ -192,3 +193,21 @@ def test_splitmix_published_vector_and_moments():
     x = noise.xi(2207, a, b, 5)
     assert abs(x.mean()) < 0.02 and abs(x.var() - 1) < 0.02
     assert np.abs(x).max() <= math.sqrt(3)
+
+
+def test_reacting_box_chemistry_is_in_the_explicit_stable_range():
+    """Workload recipe: with the default 2-step constants the explicit CO update of the
+    reacting box is contractive (lambda_CO < 1 per step): over 60 steps of an axial column
+    of the box CO stays non-negative up to WENO/diffusion round-off and T does not
+    overshoot the burnt temperature."""
+    p, P, u, sc = L.reacting_box(4, 4, 384)
+    st = S.init_state(p, t(P), t(u), t(sc))
+    for _ in range(60):
+        st, _ = S.step(p, st)
+    s = st["scal"].numpy()
+    ch, F = p["chem"], p["thickening"]
+    rho = scalars.density(p, st["scal"], Grid(p).shape).numpy()
+    lam = ch[2] / F * np.exp(-ch[3] / s[0]) * np.sqrt(rho * np.maximum(s[2], 0) / L.W_SPECIES[1])
+    assert lam.max() < 0.5
+    assert s[3].min() > -1e-5
+    assert s[0].max() < 1970.0
