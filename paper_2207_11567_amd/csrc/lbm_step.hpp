@@ -6,7 +6,8 @@
 //   -> rho (ideal gas), grad rho, diffusion + reaction right-hand sides, Lambda (Eq. 3)
 //   -> pull-streaming of the Q populations with boundary substitutions (Eq. 1)
 //   -> moments P_h, u (Eq. 7) -> WENO3 advection, explicit Euler scalar update (Sec. 2.3)
-//   -> source Xi (Eq. 2) -> pre-conditioning (Eq. 13) -> cumulant collision (Eqs. 9-12)
+//   -> source Xi (Eq. 2) -> pre-conditioning (Eq. 13) -> cumulant collision (Eqs. 9-12,
+//      optionally with Geier's Galilean correction)
 //   -> post-collision populations (Eq. 8) stored as deviations from the lattice weights
 //   -> FP64 block partial sums (wavefront shuffles + LDS), one record per block.
 // In a closed domain the thermodynamic pressure P_th = pi P_th(0) scales the ideal-gas
@@ -845,8 +846,8 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const R ugr = u[0] * gradrho[0] + u[1] * gradrho[1] + u[2] * gradrho[2];
         const R rsL = rho0 * s * Lam;
-        // Eq. 2: Xi_i = cs2 (f_eq/rho - w)(c - u).grad rho + w rho cs2 Lambda (recomputed
-        // where needed rather than held in registers across the collision)
+        // Eq. 2: Xi_i = cs2 (f_eq/rho - w)(c - u).grad rho + w rho cs2 Lambda, formed once
+        // per population and kept for the post-collision form (Eq. 8)
         auto xi_of = [&](int i) -> R {
           if constexpr (NS >= 2) {
             const R cu = R(cx(i)) * u[0] + R(cy(i)) * u[1] + (D == 3 ? R(cz(i)) * u[2] : R(0));
