@@ -420,28 +420,28 @@ __device__ __forceinline__ R density(const ThermoT<R> &t, const R (&v)[NS > 0 ? 
 template <class R> __device__ __forceinline__ R viscosity(const ThermoT<R> &t, R rho) {
   return t.const_mu ? fdiv(t.mu_ref, rho) : t.nu_ref;
 }
-
-// Jiang-Shu WENO3 face value between b and c from the upwind-biased triple (a, b, c):
-// candidates -a/2 + 3b/2 and (b + c)/2 with linear weights 1/3, 2/3, smoothness
-// (b-a)^2 and (c-b)^2, alpha = d/(eps + beta)^2.
-template <class R> __device__ __forceinline__ R weno3_face(R a, R b, R c, R eps) {
-  const R b0 = (b - a) * (b - a), b1 = (c - b) * (c - b);
-  const R e0 = eps + b0, e1 = eps + b1;
-  const R a0 = R(1.0 / 3.0) * e1 * e1, a1 = R(2.0 / 3.0) * e0 * e0;   // alpha ratios
-  return fdiv(a0 * (R(-0.5) * a + R(1.5) * b) + a1 * (R(0.5) * b + R(0.5) * c), a0 + a1);
+// The same from 1/rho, for the cell whose reciprocal density is at hand.
+template <class R> __device__ __forceinline__ R viscosity_irho(const ThermoT<R> &t, R irho) {
+  return t.const_mu ? t.mu_ref * irho : t.nu_ref;
 }
 
-// Upwind WENO3 derivative across a cell from the upwind neighbours U2, U1, the cell value
-// v0 and the downwind neighbour D1: face(U1, v0, D1) - face(U2, U1, v0), with the two
-// faces sharing the difference v0 - U1.  Each face value is b + (1/2) q with
-// q = (S1 d0 + 2 S0 d1)/(S1 + 2 S0), d0 = b - a, d1 = c - b, S = (eps + d^2)^2.
+// Upwind WENO3 derivative across a cell (Jiang-Shu weights: candidates -a/2 + 3b/2 and
+// (b + c)/2 of the upwind-biased triple (a, b, c), linear weights 1/3, 2/3, smoothness
+// (b-a)^2 and (c-b)^2, alpha = d/(eps + beta)^2) from the upwind neighbours U2, U1, the
+// cell value v0 and the downwind neighbour D1: face(U1, v0, D1) - face(U2, U1, v0), with
+// the two faces sharing the difference v0 - U1.  Each face value is b + (1/2) q with
+// q = (S1 d0 + 2 S0 d1)/(S1 + 2 S0), d0 = b - a, d1 = c - b, S = (eps + d^2)^2.  In FP64
+// the two quotients share one division (the product of the denominators stays far inside
+// the FP64 range); FP32 keeps two reciprocals, as that product can leave the FP32 range
+// for small scalar scales.
 template <class R> __device__ __forceinline__ R weno3_diff(R U2, R U1, R v0, R D1, R eps) {
   const R dA = U1 - U2, dB = v0 - U1, dC = D1 - v0;
   const R eA = eps + dA * dA, eB = eps + dB * dB, eC = eps + dC * dC;
   const R SA = eA * eA, SB = eB * eB, SC = eC * eC;
-  const R q1 = fdiv(SC * dB + R(2) * (SB * dC), SC + R(2) * SB);
-  const R q2 = fdiv(SB * dA + R(2) * (SA * dB), SB + R(2) * SA);
-  return dB + R(0.5) * (q1 - q2);
+  const R n1 = SC * dB + R(2) * (SB * dC), d1 = SC + R(2) * SB;
+  const R n2 = SB * dA + R(2) * (SA * dB), d2 = SB + R(2) * SA;
+  if constexpr (sizeof(R) == 8) return dB + R(0.5) * fdiv(n1 * d2 - n2 * d1, d1 * d2);
+  else return dB + R(0.5) * (fdiv(n1, d1) - fdiv(n2, d2));
 }
 
 }  // namespace lbm

@@ -445,6 +445,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
 #pragma unroll
       for (int k = 0; k < NS; ++k) phi0[k] = (R)bld<Sc>(slice(sin_ + (size_t)k * N), un);
       const R rho0 = NS > 0 ? density<NS, R>(a.th, phi0, pim) : R(a.th.rho_ref);
+      const R irho0 = fdiv(R(1), rho0);            // every later division by rho uses it
       const R rho_in = NS > 0 ? density<NS, R>(a.th, phin, pim) : R(a.th.rho_ref);
 
       // mixture-averaged diffusion (Hirschfelder-Curtiss fluxes with the correction flux,
@@ -535,7 +536,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             uo[1] += R(cy(j)) * gj;
             if (D == 3) uo[2] += R(cz(j)) * gj;
           }
-          const R f = fdiv(a.P0, s * rho0);
+          const R f = R(3) * R(a.P0) * irho0;
           uo[0] *= f; uo[1] *= f; uo[2] *= f;
         }
         const R uo2 = uo[0] * uo[0] + uo[1] * uo[1] + uo[2] * uo[2];
@@ -600,7 +601,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         if (D == 3 && cz(i)) mz += R(cz(i)) * gh[i];
       }
       const R P0 = R(a.P0);
-      const R mom = fdiv(P0, s * rho0);          // rho u = P0 sum c ghat / cs2
+      const R mom = R(3) * P0 * irho0;           // rho u = P0 sum c ghat / cs2
       const R u[3] = {mx * mom, my * mom, D == 3 ? mz * mom : R(0)};
 
       // ---------------------------------------------------------------- scalar stencils
@@ -613,7 +614,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
 #pragma unroll
       for (int k = 0; k < NSV; ++k) adv[k] = R(0);
       if constexpr (NS > 0) {
-        const R rhoD0 = rho0 * viscosity(a.th, rho0) * a.th.inv_Pr;
+        const R rhoD0 = rho0 * viscosity_irho(a.th, irho0) * a.th.inv_Pr;
         const R rhoD_in = rho_in * viscosity(a.th, rho_in) * a.th.inv_Pr;
         // cells whose +-2 stencil touches no face and no solid take the plain path
         bool interior = gw == GW(0);
@@ -738,7 +739,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         };
         if (interior) stencils(std::true_type{});
         else stencils(std::false_type{});
-        const R Fr = fdiv(a.th.F, rho0);
+        const R Fr = a.th.F * irho0;
 #pragma unroll
         for (int q = 0; q < NS; ++q) R_s[q] *= Fr;
         if constexpr (FULL && NS == 6) {
@@ -761,7 +762,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
           const R iT = fdiv(R(1), T);
           const R q1 = a.th.B1 * exp(-a.th.Ta1 * iT) * conc[0] * conc[1];
           const R q2 = a.th.B2 * exp(-a.th.Ta2 * iT) * conc[2] * sqrt(conc[1]);
-          const R ir = fdiv(R(1), rho0);
+          const R ir = irho0;
           // molar rates per mass: sum over reactions of nu_k,r q_r, over rho
           const R m0 = -q1 * ir, m1 = (R(-1.5) * q1 - R(0.5) * q2) * ir, m2 = (q1 - q2) * ir,
                   m3 = q2 * ir, m4 = R(2) * q1 * ir;
@@ -843,7 +844,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         }
         if (a.thermo) red[8] = w_over_T<NS>(a.th, phi1, a.inv_T_ref_d);
         // ------------------------------------------------------------ collision
-        const R r = fdiv(a.th.rho_ref, rho0);           // P0/(rho cs2)
+        const R r = a.th.rho_ref * irho0;               // P0/(rho cs2)
         const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const R ugr = u[0] * gradrho[0] + u[1] * gradrho[1] + u[2] * gradrho[2];
         const R rsL = rho0 * s * Lam;
@@ -864,7 +865,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         R Es = R(0);
         // sum_i Xi_i = cs2 (rho Lambda + u . grad rho) (the moments of Eq. 2)
         const R Xs = NS >= 2 ? s * (rho0 * Lam + ugr) : R(0);
-        const R half_rcs = fdiv(R(0.5), rho0 * s);
+        const R half_rcs = R(1.5) * irho0;               // 1/(2 rho cs2)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           if constexpr (NS >= 2) {
@@ -878,9 +879,9 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) e[i] -= R(wgt<Q>(i)) * Es;   // d = f~ - w
-        R nu = viscosity(a.th, rho0);
+        R nu = viscosity_irho(a.th, irho0);
         if constexpr (FULL && NS == 6) {
-          if (a.mx.on) nu = fdiv(mu_c, rho0);
+          if (a.mx.on) nu = mu_c * irho0;
         }
         Rates<R> rt;
         rt.tau0 = nu * R(3) + R(0.5);                    // nu / cs2 + 1/2
@@ -890,7 +891,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         rt.gal = a.gal != 0;
         const R hP0 = R(0.5) * a.invP0;
         const R base = sg + Xs * hP0;                    // (1/r) m0 - 1
-        const R invr = fdiv(rho0, a.th.rho_ref);
+        const R invr = rho0 * a.invP0 * s;              // rho/rho_ref = rho cs2/P0
         if constexpr (COLL != COLL_BGK) {
           if constexpr (Q == 9) collide_d2q9(e, u[0], u[1], rt);
           else collide_d3q27<R, COLL == COLL_CUM1>(e, u[0], u[1], u[2], rt);

@@ -145,3 +145,40 @@ def test_reduced_precision_one_step(lat, shape, phys, prec):
         err = (np.abs(g_scal - o) / scale).max()
         assert err <= 2e-6, err
     s.close()
+
+
+@pytest.mark.parametrize("phys", ["isothermal", "passive", "one_step", "two_step"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_unit_high_order_rate_instance(phys, prec):
+    """D3Q27 with every cumulant of order >= 3 relaxed at rate one (the default, which runs
+    its own kernel instance; the FP32-arithmetic two-step instance asks for four waves per
+    SIMD and spills a few values), one step from a random state with inlet, outlet and
+    walls, against the FP64 oracle at the bounds of the tests above."""
+    shape = (7, 6, 9)
+    faces = ["inlet", "outlet", "periodic", "periodic", "wall", "wall"]
+    p = _params("D3Q27", shape, phys, "cumulant", faces=faces, precision=prec, omega_high=1.0,
+                inlet_u=[0.03, 0.0, 0.0], inlet_noise=0.05)
+    ghat, scal = random_state(p, 23)
+    solid = np.random.default_rng(4).uniform(size=shape) < 0.05
+    s = make_solver(p)
+    s.set_geometry(torch.from_numpy(solid.astype(np.uint8)))
+    gpu_state(s, ghat, scal)
+    s.step(1)
+    g_pops, g_scal, _ = fetch(s)
+    s.close()
+    st, _ = OS.step(p, oracle_state(p, ghat, scal, solid))
+    o_pops = oracle_ghat(p, st)
+    fl = ~solid
+    if prec == "fp64":
+        tol_p, tol_s = 1e-12, 1e-12
+    else:
+        tol_p = 2e-7 + (np.abs(o_pops) * 2.0 ** -11 if prec == "fp16s" else 0.0)
+        tol_s = 2e-6
+    assert (np.abs(g_pops - o_pops) <= tol_p)[:, fl].all(), np.abs(g_pops - o_pops)[:, fl].max()
+    if scal.shape[0]:
+        o = st["scal"].numpy()
+        scale = np.array(p["weno_scale"][:scal.shape[0]]).reshape(-1, 1, 1, 1)
+        if prec != "fp64":
+            scale = np.maximum(scale, np.abs(o))
+        err = (np.abs(g_scal - o) / scale)[:, fl].max()
+        assert err <= tol_s, err
