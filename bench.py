@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 import lbm_inputs as L  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+VALU_ISSUE_PEAK = 256 * 2.4e9          # wave instructions per second (one per CU per cycle)
 CS2 = 1.0 / 3.0
 
 
@@ -229,7 +230,8 @@ def valu_for(name):
         rec = json.load(fh)
     if rec.get("source_hash") != source_hash():
         return None
-    return {"valu_per_wave": round(rec["valu_per_wave"], 1), "issue_frac": round(rec["valu_issue_frac"], 4),
+    return {"valu_per_wave": round(rec["valu_per_wave"], 1), "valu_insts_per_launch": rec["valu_insts"],
+            "issue_frac_profiled": round(rec["valu_issue_frac"], 4),
             "issue_limit": "one wave instruction per CU per cycle: 256 CUs x 2.4 GHz = 614 G/s"}
 
 
@@ -419,7 +421,10 @@ def main():
     extra = {}
     valu = valu_for(args.workload)
     if valu is not None:
+        # the step's other limit: VALU issue (counted instructions over the live launch time)
+        valu["issue_frac"] = round(valu["valu_insts_per_launch"] / (main_res["ms_per_step"] * 1e-3) / VALU_ISSUE_PEAK, 4)
         extra["step_kernel_valu"] = valu
+        roofline["valu_issue_frac"] = valu["issue_frac"]
     extra["hbm_copy_gbs"] = round(copy_gbs, 1)
     extra["frac_of_copy"] = round(achieved / copy_gbs, 4)
     if not args.no_extra:

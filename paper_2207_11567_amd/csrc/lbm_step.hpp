@@ -251,14 +251,6 @@ template <class T> __device__ __forceinline__ T ldg(const T *base, unsigned idx)
 template <class T> __device__ __forceinline__ void stg(T *base, unsigned idx, T v) {
   *(T *)((char *)base + idx * (unsigned)sizeof(T)) = v;
 }
-// Streaming (non-temporal) variants for the populations, which are read once and written
-// once per step: they should not displace the reused scalar rows and planes from L2.
-template <class T> __device__ __forceinline__ T ldg_nt(const T *base, unsigned idx) {
-  return __builtin_nontemporal_load((const T *)((const char *)base + idx * (unsigned)sizeof(T)));
-}
-template <class T> __device__ __forceinline__ void stg_nt(T *base, unsigned idx, T v) {
-  __builtin_nontemporal_store(v, (T *)((char *)base + idx * (unsigned)sizeof(T)));
-}
 
 // Raw buffer access: one descriptor (SGPRs) per array slice (a population or a scalar
 // field, under 4 GiB since Q N < 2^31 elements) and a 32-bit byte offset per lane, so the
