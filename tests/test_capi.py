@@ -60,3 +60,12 @@ def test_sizes_of_valid_parameters():
     N = 16 * 16 * 32
     assert pb.value == 27 * N * 4 and sb.value == 6 * N * 4
     assert wb.value >= N * 8 + (N // 256) * 72
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No fallback: without the built HIP library the binding raises instead of running
+    anything else."""
+    from paper_2207_11567_amd import _capi as C
+    monkeypatch.setattr(C, "LIB_PATH", os.path.join(ROOT, "_no_such_dir", "liblbm.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        C._load()
