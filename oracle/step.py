@@ -6,7 +6,8 @@ scalars (T, Y_1..) at level n, and the step counter n.  One step, for every cell
  1. pull g_i(r, n) = g*_i(r - c_i, n-1) with boundary substitutions (below);
  2. rho^n from the ideal gas; non-advective RHS R and Lambda (Eq. 3);
  3. P_h, u from Eq. 7;  4. grad(rho) by central differences;  5. Xi (Eq. 2);
- 6. f' (Eq. 13);  7. collision (cumulant, Eq. 9 as read; or BGK in the same frame);
+ 6. f' (Eq. 13);  7. collision (cumulant, Eq. 9 as read, optionally with the Galilean
+    correction of the cumulant module; or BGK in the same frame);
  8. g* (Eq. 8);  9. explicit Euler update of the scalars with u^n (Sec. 2.3);
 10. FP64 sums over fluid cells at level n;
 11. closed domains only: the thermodynamic pressure of level n+1 from mass conservation
