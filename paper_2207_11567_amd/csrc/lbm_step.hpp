@@ -824,13 +824,15 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             }
         }
         // ------------------------------------------------------------ scalar update
-        bool bad = false;
+        // one finiteness test for the step's outputs: a NaN or an infinity in any of
+        // them makes the sum non-finite (the finite values are far below overflow)
+        R chk = R(0);
         R phi1[NSV];
         phi1[0] = R(0);
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
           const R nv = phi0[q] + (R_s[q] - adv[q]);
-          bad |= !isfinite(nv);
+          chk += nv;
           bst<Sc>(slice(sout + (size_t)q * N), un, (Sc)nv);
           phi1[q] = (R)(Sc)nv;
         }
@@ -909,8 +911,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             bst<St, 2>(slice(pout + (size_t)i * N), un, encode<St>(gp - om * (gp - geq) + xh));
           }
         }
-        bad |= !isfinite(Ph + u[0] + u[1] + u[2]);
-        if (bad) atomicOr(a.flag, 1);
+        if (!isfinite(chk + Ph + u[0] + u[1] + u[2])) atomicOr(a.flag, 1);
       }
 
       // ---------------------------------------------------------------- FP64 sums

@@ -182,3 +182,24 @@ def test_unit_high_order_rate_instance(phys, prec):
             scale = np.maximum(scale, np.abs(o))
         err = (np.abs(g_scal - o) / scale)[:, fl].max()
         assert err <= tol_s, err
+
+
+@pytest.mark.parametrize("where", ["population", "scalar"])
+def test_non_finite_value_is_reported(where):
+    """A NaN in one cell's population or scalar makes the step's outputs non-finite; the
+    kernel's finiteness test flags it and the next synchronising call reports the
+    divergence status."""
+    from paper_2207_11567_amd._capi import LBM_E_DIVERGED, LbmError
+    p = _params("D2Q9", (1, 13, 70), "one_step", "cumulant")
+    ghat, scal = random_state(p, 31)
+    if where == "population":
+        ghat[4, 0, 6, 33] = np.nan
+    else:
+        scal[0, 0, 6, 33] = np.nan
+    s = make_solver(p)
+    gpu_state(s, ghat, scal)
+    s.step(1)
+    with pytest.raises(LbmError) as exc:
+        s.step_sums()
+    assert exc.value.status == LBM_E_DIVERGED
+    s.close()
