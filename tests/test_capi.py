@@ -39,6 +39,8 @@ def test_exports_every_declared_symbol():
      "closed domain"),
     ({"pth_mode": "closed", "gamma": 1.0}, "gamma"),
     ({"galilean": 2}, "galilean"),
+    ({"lattice": "D3Q27", "nx": 1024, "ny": 1024, "nz": 100}, "too large"),
+    ({"nx": 0}, ">= 1"),
     ({"galilean": 1, "collision": "bgk"}, "cumulant"),
 ])
 def test_validation_rejects(change, needle):

@@ -203,3 +203,25 @@ def test_non_finite_value_is_reported(where):
         s.step_sums()
     assert exc.value.status == LBM_E_DIVERGED
     s.close()
+
+
+@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 1, 1)), ("D2Q9", (1, 2, 1)), ("D3Q27", (1, 1, 1)),
+                                       ("D3Q27", (2, 1, 3))])
+def test_degenerate_periodic_extents(lat, shape):
+    """Periodic extents of one and two cells: every stencil point wraps onto the cell
+    itself or its single neighbour (two wraps for the +-2 points), against the oracle."""
+    p = _params(lat, shape, "one_step", "cumulant", faces=["periodic"] * 6)
+    ghat, scal = random_state(p, 37)
+    _compare(p, ghat, scal, 3)
+
+
+def test_zero_steps_leave_the_state():
+    p = _params("D3Q27", (7, 6, 9), "two_step", "cumulant")
+    ghat, scal = random_state(p, 41)
+    s = make_solver(p)
+    gpu_state(s, ghat, scal, step=5)
+    s.step(0)
+    g_pops, g_scal, step = fetch(s)
+    s.close()
+    assert step == 5
+    assert np.array_equal(g_pops, ghat) and np.array_equal(g_scal, scal)
