@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "lbm_launch.hpp"
@@ -25,8 +26,11 @@ struct lbm_solver {
   int Q, NS, D, prec, nblocks;
   int *flag;
   double *sums;
-  double *partials;   // [nblocks][NSUM]: block records of lbm_step
+  double *partials;   // block records of lbm_step: [nblocks] interior, then [list blocks]
   double *aux;        // block records of field extraction, flame surface and objective
+  int *cells;         // linear indices of the boundary cells (the step's list half)
+  int ncells;         // their number
+  int nrec;           // block records the last step wrote
   double *stage;
   double *thermo;     // (pi, q, K) of the closed-domain thermodynamic pressure
   bool closed;
@@ -61,7 +65,8 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   long long N;
   int Q, NS, D, nblocks;
-  size_t pop_bytes, scal_bytes, off_flag, off_sums, off_thermo, off_stage, off_partials, off_geom, work_bytes;
+  size_t pop_bytes, scal_bytes, off_flag, off_sums, off_thermo, off_stage, off_partials, off_geom, off_cells,
+      work_bytes;
 };
 
 static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
@@ -137,7 +142,9 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   L->NS = NS;
   L->D = Dm;
   L->nblocks = (int)((N + 255) / 256);
-  const int nrec = 2 * L->nblocks;         // step records, then those of the other reductions
+  // step records (interior tiles, then list blocks, each at most nblocks), then those of
+  // the other reductions
+  const int nrec = 3 * L->nblocks;
   L->pop_bytes = (size_t)Q * N * pop_elem(p->precision);
   L->scal_bytes = (size_t)NS * N * scal_elem(p->precision);
   L->off_flag = 0;
@@ -146,7 +153,8 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   L->off_stage = 256;
   L->off_partials = L->off_stage + 256 * NSUM * sizeof(double);
   L->off_geom = align256(L->off_partials + (size_t)nrec * NSUM * sizeof(double));
-  L->work_bytes = align256(L->off_geom + (size_t)N * (Q == 9 ? 4 : 8));
+  L->off_cells = align256(L->off_geom + (size_t)N * (Q == 9 ? 4 : 8));
+  L->work_bytes = align256(L->off_cells + (size_t)N * sizeof(int));
   return LBM_OK;
 }
 
@@ -259,6 +267,75 @@ static lbm_status check_flag(lbm_solver *s) {
   return LBM_OK;
 }
 
+// The boundary cells of the split step, in increasing linear index: a non-zero geometry
+// word or a non-periodic face within two cells on some axis (the rule of near_face and the
+// interior instance).  Built on the host from the geometry words; synchronises.
+static bool host_near_face(int c, int n, int flo, int fhi) { return (flo >= 0 && c < 2) || (fhi >= 0 && c >= n - 2); }
+
+static hipError_t build_cell_list(lbm_solver *s) {
+  const lbm_params &p = s->p;
+  StepArgs a = make_args(s);
+  const long long N = s->N;
+  const size_t gsz = s->Q == 9 ? 4 : 8;
+  std::vector<unsigned char> gw;
+  hipError_t e = hipSuccess;
+  if (s->has_geom) {
+    gw.resize((size_t)N * gsz);
+    e = hipMemcpyAsync(gw.data(), s->geom, gw.size(), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return e;
+  }
+  std::vector<int> list;
+  for (int z = 0; z < p.nz; ++z)
+    for (int y = 0; y < p.ny; ++y) {
+      const bool row = host_near_face(y, p.ny, a.face[2], a.face[3]) || host_near_face(z, p.nz, a.face[4], a.face[5]);
+      for (int x = 0; x < p.nx; ++x) {
+        const long long n = x + (long long)p.nx * (y + (long long)p.ny * z);
+        bool g = row || host_near_face(x, p.nx, a.face[0], a.face[1]);
+        if (!g && s->has_geom) {
+          const unsigned char *w = gw.data() + (size_t)n * gsz;
+          for (size_t b = 0; b < gsz; ++b) g = g || w[b] != 0;
+        }
+        if (g) list.push_back((int)n);
+      }
+    }
+  s->ncells = (int)list.size();
+  if (!list.empty()) {
+    e = hipMemcpyAsync(s->cells, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  }
+  return e;
+}
+
+// One step from a.pop_in / a.scal_in, either as one instance over every cell or split into
+// the interior instance over the tile grid and the list instance over the boundary cells.
+// The split pays where the all-cell instance carries boundary code that costs the interior
+// cells occupancy: curved walls (the FULL instance; its list half is FULL) and the FP64
+// two-step step on large grids; with observables or mixture transport the step stays one
+// FULL instance.  On small grids the second launch would add a full pass of latency.  The
+// interior half writes block records [0, nblocks), the list half the records after them.
+static hipError_t launch_step_pass(lbm_solver *s, const StepArgs &a0) {
+  StepArgs a = a0;
+  a.partials = s->partials;
+  const bool split = !(a.stats || a.probe_out || a.mix) &&
+                     (a.lvl || (s->prec == LBM_FP64 && s->NS == 6 && s->nblocks >= 4096));
+  if (!split) {
+    s->nrec = s->nblocks;
+    return launch(s, LAUNCH_STEP, a);
+  }
+  hipError_t e = launch(s, LAUNCH_STEP_INTERIOR, a);
+  s->nrec = s->nblocks;
+  if (e != hipSuccess || s->ncells == 0) return e;
+  a.cells = s->cells;
+  a.ncells = s->ncells;
+  a.partials = s->partials + (size_t)s->nblocks * NSUM;
+  const int nlb = (s->ncells + 255) / 256;
+  if (s->Q == 9) e = launch_d2q9(s->prec, s->NS, LAUNCH_STEP_LIST, a, nlb, s->stream, nullptr, nullptr, nullptr);
+  else e = launch_d3q27(s->prec, s->NS, LAUNCH_STEP_LIST, a, nlb, s->stream, nullptr, nullptr, nullptr);
+  s->nrec = s->nblocks + nlb;
+  return e;
+}
+
 extern "C" {
 
 lbm_status lbm_query_sizes(const lbm_params *p, size_t *pop_bytes, size_t *scal_bytes, size_t *work_bytes) {
@@ -307,7 +384,10 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
   s->flag = (int *)(s->work + L.off_flag);
   s->sums = (double *)(s->work + L.off_sums);
   s->partials = (double *)(s->work + L.off_partials);
-  s->aux = s->partials + (size_t)L.nblocks * NSUM;
+  s->aux = s->partials + (size_t)2 * L.nblocks * NSUM;
+  s->cells = (int *)(s->work + L.off_cells);
+  s->ncells = 0;
+  s->nrec = L.nblocks;
   s->stage = (double *)(s->work + L.off_stage);
   s->thermo = (double *)(s->work + L.off_thermo);
   s->closed = p->pth_mode == LBM_PTH_CLOSED;
@@ -321,8 +401,9 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
   s->geom = s->work + L.off_geom;
   hipError_t e = hipMemsetAsync(s->work, 0, 256, s->stream);
   if (e == hipSuccess) e = launch_set_thermo(s->thermo, 1.0, 0.0, 0.0, s->stream);
+  if (e == hipSuccess) e = build_cell_list(s);
   if (e != hipSuccess) {
-    g_create_err = std::string("clearing the work buffer: ") + hipGetErrorString(e);
+    g_create_err = std::string("setting up the work buffer: ") + hipGetErrorString(e);
     delete s;
     return LBM_E_HIP;
   }
@@ -335,12 +416,15 @@ lbm_status lbm_set_geometry(lbm_solver *s, const uint8_t *solid_dev) {
   s->lvl = nullptr;
   if (!solid_dev) {
     s->has_geom = false;
-    return LBM_OK;
+    hipError_t e = build_cell_list(s);
+    return e == hipSuccess ? LBM_OK : hip_fail(s, e, "boundary cell list");
   }
   StepArgs a = make_args(s);
   hipError_t e = launch_geometry(s->Q, solid_dev, s->geom, s->p.nx, s->p.ny, s->p.nz, s->N, a.face, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "geometry kernel");
   s->has_geom = true;
+  e = build_cell_list(s);
+  if (e != hipSuccess) return hip_fail(s, e, "boundary cell list");
   return LBM_OK;
 }
 
@@ -349,7 +433,8 @@ lbm_status lbm_set_wall_distance(lbm_solver *s, const double *phi_dev) {
   s->lvl = nullptr;
   if (!phi_dev) {
     s->has_geom = false;
-    return LBM_OK;
+    hipError_t e = build_cell_list(s);
+    return e == hipSuccess ? LBM_OK : hip_fail(s, e, "boundary cell list");
   }
   StepArgs a = make_args(s);
   hipError_t e = launch_geometry_levelset(s->Q, phi_dev, s->geom, s->p.nx, s->p.ny, s->p.nz, s->N, a.face,
@@ -357,6 +442,8 @@ lbm_status lbm_set_wall_distance(lbm_solver *s, const double *phi_dev) {
   if (e != hipSuccess) return hip_fail(s, e, "geometry kernel");
   s->has_geom = true;
   s->lvl = phi_dev;
+  e = build_cell_list(s);
+  if (e != hipSuccess) return hip_fail(s, e, "boundary cell list");
   return LBM_OK;
 }
 
@@ -410,10 +497,10 @@ lbm_status lbm_step(lbm_solver *s, int32_t nsteps) {
       for (int j = 0; j < 8; ++j) a.probe[j] = s->probe[j];
       s->probe_rows += 1;
     }
-    hipError_t e = launch(s, LAUNCH_STEP, a);
+    hipError_t e = launch_step_pass(s, a);
     if (e != hipSuccess) return hip_fail(s, e, "step kernel");
     if (s->closed) {
-      e = launch_finalize(s->partials, s->nblocks, s->stage, s->sums, s->stream, s->thermo);
+      e = launch_finalize(s->partials, s->nrec, s->stage, s->sums, s->stream, s->thermo);
       if (e != hipSuccess) return hip_fail(s, e, "thermodynamic pressure update");
     }
     s->cur ^= 1;
@@ -440,14 +527,14 @@ lbm_status lbm_step_from(lbm_solver *s, const void *pops_in, const void *scal_in
   a.scal_in = scal_in;
   a.scal_out = scal_out;
   a.step = step;
-  hipError_t e = launch(s, LAUNCH_STEP, a);
+  hipError_t e = launch_step_pass(s, a);
   if (e != hipSuccess) return hip_fail(s, e, "step kernel");
   return LBM_OK;
 }
 
 lbm_status lbm_step_sums(lbm_solver *s, double *sums_host) {
   if (!s) return LBM_E_INVALID;
-  hipError_t e = launch_finalize(s->partials, s->nblocks, s->stage, s->sums, s->stream);
+  hipError_t e = launch_finalize(s->partials, s->nrec, s->stage, s->sums, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "finalize kernel");
   if (sums_host) {
     e = hipMemcpyAsync(sums_host, s->sums, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream);

@@ -6,7 +6,11 @@
 
 namespace lbm {
 
-enum LaunchKind { LAUNCH_STEP = 0, LAUNCH_EXTRACT = 1, LAUNCH_INIT = 2 };
+// LAUNCH_STEP: every cell in one instance (FULL with curved walls, observables or mixture
+// transport); LAUNCH_STEP_INTERIOR / LAUNCH_STEP_LIST: the two halves of a split step
+// (interior cells on the tile grid, then the listed boundary cells, FULL when curved walls
+// are bound).
+enum LaunchKind { LAUNCH_STEP = 0, LAUNCH_EXTRACT = 1, LAUNCH_INIT = 2, LAUNCH_STEP_INTERIOR = 3, LAUNCH_STEP_LIST = 4 };
 
 // Returns hipSuccess or the launch error.  nblocks covers N cells with 256 threads.
 hipError_t launch_d2q9(int prec, int ns, int kind, const StepArgs &a, int nblocks, hipStream_t st,
@@ -41,23 +45,23 @@ int collision_instance(const StepArgs &a) {
   return (Q == 27 && (R)a.wh != R(1)) ? COLL_CUM : COLL_CUM1;
 }
 
-template <int Q, int PREC, int NS, bool FULL>
+template <int Q, int PREC, int NS, bool FULL, int MODE>
 hipError_t launch_step(const StepArgs &a, int nblocks, hipStream_t st) {
   using R = typename Prec<PREC>::R;
   switch (collision_instance<Q, PREC>(a)) {
     case COLL_CUM1:
-      hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, FULL, COLL_CUM1>), dim3(nblocks), dim3(256), 0, st,
+      hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, FULL, COLL_CUM1, MODE>), dim3(nblocks), dim3(256), 0, st,
                          to_kargs<R>(a));
       break;
     case COLL_CUM:
       if constexpr (Q == 27)
-        hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, FULL, COLL_CUM>), dim3(nblocks), dim3(256), 0, st,
+        hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, FULL, COLL_CUM, MODE>), dim3(nblocks), dim3(256), 0, st,
                            to_kargs<R>(a));
       else
         return hipErrorInvalidValue;
       break;
     default:
-      hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, FULL, COLL_BGK>), dim3(nblocks), dim3(256), 0, st,
+      hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, FULL, COLL_BGK, MODE>), dim3(nblocks), dim3(256), 0, st,
                          to_kargs<R>(a));
   }
   return hipGetLastError();
@@ -68,19 +72,26 @@ hipError_t launch_one(int kind, const StepArgs &a, int nblocks, hipStream_t st, 
                       const double *u, const double *scal) {
   using R = typename Prec<PREC>::R;
   const bool full = a.lvl || a.stats || a.probe_out || a.mix;
-  if (kind == LAUNCH_STEP && full)
-    return launch_step<Q, PREC, NS, true>(a, nblocks, st);
-  else if (kind == LAUNCH_STEP)
-    return launch_step<Q, PREC, NS, false>(a, nblocks, st);
-  else if (kind == LAUNCH_EXTRACT && full)   // no collision on the extract path
-    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, true, COLL_CUM1>), dim3(nblocks), dim3(256), 0, st,
-                       to_kargs<R>(a));
-  else if (kind == LAUNCH_EXTRACT)
-    hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, false, COLL_CUM1>), dim3(nblocks), dim3(256), 0, st,
-                       to_kargs<R>(a));
-  else
-    hipLaunchKernelGGL((init_kernel<Q, PREC, NS>), dim3(nblocks), dim3(256), 0, st, to_kargs<double>(a), Ph,
-                       u, scal);
+  switch (kind) {
+    case LAUNCH_STEP:
+      return full ? launch_step<Q, PREC, NS, true, MODE_ALL>(a, nblocks, st)
+                  : launch_step<Q, PREC, NS, false, MODE_ALL>(a, nblocks, st);
+    case LAUNCH_STEP_INTERIOR: return launch_step<Q, PREC, NS, false, MODE_INTERIOR>(a, nblocks, st);
+    case LAUNCH_STEP_LIST:
+      return a.lvl ? launch_step<Q, PREC, NS, true, MODE_LIST>(a, nblocks, st)
+                   : launch_step<Q, PREC, NS, false, MODE_LIST>(a, nblocks, st);
+    case LAUNCH_EXTRACT:   // no collision on the extract path
+      if (full)
+        hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, true, COLL_CUM1, MODE_ALL>), dim3(nblocks), dim3(256), 0,
+                           st, to_kargs<R>(a));
+      else
+        hipLaunchKernelGGL((step_kernel<Q, PREC, NS, true, false, COLL_CUM1, MODE_ALL>), dim3(nblocks), dim3(256), 0,
+                           st, to_kargs<R>(a));
+      break;
+    default:
+      hipLaunchKernelGGL((init_kernel<Q, PREC, NS>), dim3(nblocks), dim3(256), 0, st, to_kargs<double>(a), Ph, u,
+                         scal);
+  }
   return hipGetLastError();
 }
 

@@ -30,6 +30,10 @@ namespace lbm {
 constexpr int NSUM = 9;
 // collision operator compiled into a step instance
 enum : int { COLL_CUM1 = 0, COLL_CUM = 1, COLL_BGK = 2 };
+// cells a step instance updates: every cell (tile grid), the interior cells only (tile grid;
+// the code of boundaries, solids and curved walls is not compiled in), or the cells of a
+// list (one thread per listed cell: the cells the interior instance leaves)
+enum : int { MODE_ALL = 0, MODE_INTERIOR = 1, MODE_LIST = 2 };
 
 // Host-side description of one launch (double precision constants).
 struct Thermo {
@@ -58,6 +62,8 @@ struct StepArgs {
   double transport[32];  // binary D0 (15), c_p a_k (6), b_k (6), exponents of mu and D
   double mix_in[19];   // inlet transport point: lambda, rho D_k W_k/W (6), X_k (6), Y_k (6)
   double *f_P, *f_rho, *f_u, *f_scal;   // field outputs (extract mode)
+  const int *cells;    // MODE_LIST: linear indices of the cells to update
+  int ncells;
   int nx, ny, nz;
   long long N;
   int face[6];         // ST_* code of each face, -1 for periodic
@@ -93,6 +99,8 @@ template <class R> struct KArgs {
   int nprobe;
   int probe[8];
   double *f_P, *f_rho, *f_u, *f_scal;
+  const int *cells;
+  int ncells;
   int nx, ny, nz, N;
   int face[6];
   long long step;
@@ -115,6 +123,7 @@ template <class R> KArgs<R> to_kargs(const StepArgs &a) {
   for (int j = 0; j < 8; ++j) k.probe[j] = a.probe[j];
   k.kap = (R)a.kappa;
   k.f_P = a.f_P; k.f_rho = a.f_rho; k.f_u = a.f_u; k.f_scal = a.f_scal;
+  k.cells = a.cells; k.ncells = a.ncells;
   k.nx = a.nx; k.ny = a.ny; k.nz = a.nz; k.N = (int)a.N;
   for (int f = 0; f < 6; ++f) k.face[f] = a.face[f];
   k.step = a.step; k.collision = a.collision; k.remap = a.remap; k.band_rows = a.band_rows;
@@ -243,6 +252,15 @@ __device__ __forceinline__ void axis_offsets(int c, int n, int flo, int fhi, int
   }
 }
 
+// A cell needs the general (boundary) code when its geometry word is not zero (it is
+// solid, or a solid lies within its links or its +-2 stencil) or a non-periodic face lies
+// within two cells on some axis; every other cell is interior.  The host builds the list
+// of general cells with the same rule (lbm_capi.hip), so the interior and list instances
+// of a step cover every cell exactly once.
+__device__ __forceinline__ bool near_face(int c, int n, int flo, int fhi) {
+  return (flo >= 0 && c < 2) || (fhi >= 0 && c >= n - 2);
+}
+
 // Element access through a wave-uniform base pointer and a 32-bit byte offset, so that
 // the compiler can address with the scalar base + vector offset form.
 template <class T> __device__ __forceinline__ T ldg(const T *base, unsigned idx) {
@@ -336,12 +354,13 @@ __device__ __forceinline__ double w_over_T(const ThermoT<R> &t, const R (&v)[NS 
 // SIMD (at most 128 VGPRs): its allocation otherwise lands a few registers above that, at
 // three waves; the few spilled values cost less than the lost wave (measured 9 % faster on
 // the reacting box in both storage precisions).
-template <int Q, int PREC, int NS, bool EXTRACT, bool FULL, int COLL>
+template <int Q, int PREC, int NS, bool EXTRACT, bool FULL, int COLL, int MODE>
 constexpr int step_waves_per_eu() {
-  return (Q == 27 && PREC != 0 && NS == 6 && !EXTRACT && !FULL && COLL == COLL_CUM1) ? 4 : 1;
+  return (Q == 27 && PREC != 0 && NS == 6 && !EXTRACT && !FULL && COLL == COLL_CUM1 && MODE != MODE_LIST) ? 4 : 1;
 }
-template <int Q, int PREC, int NS, bool EXTRACT, bool FULL, int COLL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<Q, PREC, NS, EXTRACT, FULL, COLL>())))
+template <int Q, int PREC, int NS, bool EXTRACT, bool FULL, int COLL, int MODE>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(step_waves_per_eu<Q, PREC, NS, EXTRACT, FULL, COLL, MODE>())))
 void step_kernel(KArgs<typename Prec<PREC>::R> a) {
   using P = Prec<PREC>;
   using St = typename P::St;
@@ -357,7 +376,17 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
   // plane by plane, so the +-1 and +-2 planes of the scalar stencils were touched a few
   // dozen tiles earlier and are still in L2.
   int n, x, y, z;
-  if (a.band_rows) {
+  bool listed = true;
+  if constexpr (MODE == MODE_LIST) {
+    const int idx = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
+    listed = idx < a.ncells;
+    n = listed ? a.cells[idx] : 0;
+    const int nxy = a.nx * a.ny;
+    z = n / nxy;
+    const int rem = n - z * nxy;
+    y = rem / a.nx;
+    x = rem - y * a.nx;
+  } else if (a.band_rows) {
     const int nxt = a.nx >> 6, bt = a.band_rows >> 2;
     const int per_plane = nxt * bt, per_band = per_plane * a.nz;
     const int band = tile / per_band, r = tile - band * per_band;
@@ -383,10 +412,14 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
   const Sc *__restrict__ sin_ = (const Sc *)a.scal_in;
   Sc *__restrict__ sout = (Sc *)a.scal_out;
 
-  if (n < N) {
+  bool active = listed && n < N;
+  const GW gw = active && a.geom ? ((const GW *)a.geom)[n] : GW(0);
+  if constexpr (MODE == MODE_INTERIOR)
+    active = active && gw == GW(0) && !near_face(x, a.nx, a.face[0], a.face[1]) &&
+             !near_face(y, a.ny, a.face[2], a.face[3]) && !near_face(z, a.nz, a.face[4], a.face[5]);
+  if (active) {
     const int nxy = a.nx * a.ny;
-    const GW gw = a.geom ? ((const GW *)a.geom)[n] : GW(0);
-    if (gw & (GW(1) << bit_self<Q>())) {
+    if (MODE != MODE_INTERIOR && (gw & (GW(1) << bit_self<Q>()))) {
       if (!EXTRACT) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) pout[i * N + n] = pin[i * N + n];
@@ -493,13 +526,13 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
       const bool border = code[0][1] >= 0 || code[0][3] >= 0 || code[1][1] >= 0 || code[1][3] >= 0 ||
                           (D == 3 && (code[2][1] >= 0 || code[2][3] >= 0));
       constexpr GW linkmask = (GW(1) << Q) - GW(1);
-      if (!border && !(gw & linkmask)) {
+      if (MODE == MODE_INTERIOR || (!border && !(gw & linkmask))) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const unsigned m = un + (unsigned)(off[0][2 - cx(i)] + off[1][2 - cy(i)] + (D == 3 ? off[2][2 - cz(i)] : 0));
           gh[i] = decode<R>(bld<St, 2>(slice(pin + (size_t)i * N), m));
         }
-      } else {
+      } else if constexpr (MODE != MODE_INTERIOR) {
         // boundary cell: bounce-back, moving-wall inlet, anti-bounce-back outlet
         R uw_in[3] = {R(a.inlet_u[0]), R(a.inlet_u[1]), R(a.inlet_u[2])};
         if (a.inlet_noise != 0.0) {
@@ -729,8 +762,8 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             }
           }
         };
-        if (interior) stencils(std::true_type{});
-        else stencils(std::false_type{});
+        if (MODE == MODE_INTERIOR || interior) stencils(std::true_type{});
+        else if constexpr (MODE != MODE_INTERIOR) stencils(std::false_type{});
         const R Fr = a.th.F * irho0;
 #pragma unroll
         for (int q = 0; q < NS; ++q) R_s[q] *= Fr;
@@ -926,7 +959,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
       if constexpr (NS >= 2) red[7] = (double)(rho0 * phi0[1]);
     }
   }
-  block_sums(red, a.partials + (size_t)tile * NSUM);
+  block_sums(red, a.partials + (size_t)(MODE == MODE_LIST ? (int)blockIdx.x : tile) * NSUM);
 }
 
 

@@ -157,6 +157,17 @@ def test_reacting_box_full_size_windows():
         _check(res, "fp32", 2)
 
 
+def test_reacting_box_fp64_full_size_windows():
+    """The reacting box in FP64: on this size the step runs split into the interior
+    instance and the list instance over the inlet and outlet planes."""
+    params, P, u, scal = L.reacting_box()
+    params["precision"] = "fp64"
+    full = _gpu_run(params, P, u, scal, None, 2)
+    for origin, size in (((50, 60, 0), (12, 12, 10)), ((90, 100, 184), (12, 12, 16)),
+                         ((180, 3, 374), (12, 12, 10))):
+        _check(_window(params, full, None, origin, size), "fp64", 2)
+
+
 def test_reacting_box_mixture_transport_full_size_windows():
     """The reacting box with mixture-averaged transport (FULL kernel instance)."""
     params, P, u, scal = L.reacting_box()
