@@ -31,6 +31,19 @@ struct lbm_solver {
   int *cells;         // linear indices of the boundary cells (the step's list half)
   int ncells;         // their number
   int nrec;           // block records the last step wrote
+  // the list half of a split step runs on a side stream (default priority), forked from
+  // and joined back into the caller's stream around each step; created on first use
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_join;
+  bool side_ready;
+  ~lbm_solver() {
+    if (side_ready) {
+      hipStreamSynchronize(side);
+      hipEventDestroy(ev_fork);
+      hipEventDestroy(ev_join);
+      hipStreamDestroy(side);
+    }
+  }
   double *stage;
   double *thermo;     // (pi, q, K) of the closed-domain thermodynamic pressure
   bool closed;
@@ -317,21 +330,37 @@ static hipError_t build_cell_list(lbm_solver *s) {
 static hipError_t launch_step_pass(lbm_solver *s, const StepArgs &a0) {
   StepArgs a = a0;
   a.partials = s->partials;
-  const bool split = !(a.stats || a.probe_out || a.mix) &&
-                     (a.lvl || (s->prec == LBM_FP64 && s->NS == 6 && s->nblocks >= 4096));
+  const bool split = !(a.stats || a.probe_out || a.mix) && (a.lvl || (s->NS == 6 && s->nblocks >= 4096));
   if (!split) {
     s->nrec = s->nblocks;
     return launch(s, LAUNCH_STEP, a);
   }
-  hipError_t e = launch(s, LAUNCH_STEP_INTERIOR, a);
+  hipError_t e = hipSuccess;
   s->nrec = s->nblocks;
-  if (e != hipSuccess || s->ncells == 0) return e;
-  a.cells = s->cells;
-  a.ncells = s->ncells;
-  a.partials = s->partials + (size_t)s->nblocks * NSUM;
+  if (s->ncells == 0) return launch(s, LAUNCH_STEP_INTERIOR, a);
+  if (!s->side_ready) {
+    e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    s->side_ready = true;
+  }
+  // fork: the list half waits for everything before this step on the caller's stream,
+  // then runs beside the interior half (the two write disjoint cells and records)
+  StepArgs b = a;
+  b.cells = s->cells;
+  b.ncells = s->ncells;
+  b.partials = s->partials + (size_t)s->nblocks * NSUM;
   const int nlb = (s->ncells + 255) / 256;
-  if (s->Q == 9) e = launch_d2q9(s->prec, s->NS, LAUNCH_STEP_LIST, a, nlb, s->stream, nullptr, nullptr, nullptr);
-  else e = launch_d3q27(s->prec, s->NS, LAUNCH_STEP_LIST, a, nlb, s->stream, nullptr, nullptr, nullptr);
+  e = hipEventRecord(s->ev_fork, s->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s->side, s->ev_fork, 0);
+  if (e != hipSuccess) return e;
+  if (s->Q == 9) e = launch_d2q9(s->prec, s->NS, LAUNCH_STEP_LIST, b, nlb, s->side, nullptr, nullptr, nullptr);
+  else e = launch_d3q27(s->prec, s->NS, LAUNCH_STEP_LIST, b, nlb, s->side, nullptr, nullptr, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(s->ev_join, s->side);
+  if (e == hipSuccess) e = launch(s, LAUNCH_STEP_INTERIOR, a);
+  // join: later work on the caller's stream sees both halves
+  if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->ev_join, 0);
   s->nrec = s->nblocks + nlb;
   return e;
 }
@@ -388,6 +417,7 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
   s->cells = (int *)(s->work + L.off_cells);
   s->ncells = 0;
   s->nrec = L.nblocks;
+  s->side_ready = false;
   s->stage = (double *)(s->work + L.off_stage);
   s->thermo = (double *)(s->work + L.off_thermo);
   s->closed = p->pth_mode == LBM_PTH_CLOSED;
