@@ -40,8 +40,12 @@
  *
  * Ownership: every device buffer is allocated by the caller and passed as a device
  * pointer; the library keeps the pointers for the solver's lifetime, never frees them and
- * allocates no device memory of its own.  All work is queued on the caller's HIP stream;
- * lbm_step does not synchronise, lbm_fields and the state copies do.
+ * allocates no device memory of its own.  All work is ordered on the caller's HIP stream:
+ * where a step runs split (boundary cells in a second kernel), that kernel runs on a side
+ * stream the solver creates on first use, forked from the caller's stream by an event
+ * before the step and joined back into it after, so later work on the caller's stream sees
+ * the whole step.  lbm_step does not synchronise, lbm_fields and the state copies do;
+ * lbm_destroy waits for the side stream.
  * Errors: every call returns an lbm_status; lbm_last_error gives a message.  A
  * non-finite value produced by a step raises a device flag reported as LBM_E_DIVERGED by
  * the next synchronising call.
