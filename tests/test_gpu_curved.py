@@ -155,3 +155,29 @@ def test_circular_cavity_at_scale():
     print("cavity rate errors", rates, flush=True)
     assert abs(rates[True]) < 1e-3
     assert abs(rates[False]) > 2 * abs(rates[True])
+
+
+@pytest.mark.parametrize("lat,shape,phys", [("D2Q9", (1, 13, 70), "one_step"), ("D3Q27", (8, 8, 64), "two_step")])
+def test_curved_closed_domain_parity(lat, shape, phys):
+    """Curved walls in a closed domain: the step runs split (interior and boundary-list
+    instances), and the thermodynamic pressure comes from the block records of both."""
+    p = _params(lat, shape, phys, "cumulant")
+    p["pth_mode"] = "closed"
+    phi = _levelset(shape, 2 if lat == "D2Q9" else 3)
+    ghat, scal = random_state(p, 35)
+    s = make_solver(p)
+    s.set_wall_distance(torch.from_numpy(phi))
+    gpu_state(s, ghat, scal)
+    s.step(4)
+    g_pops, g_scal, _ = fetch(s)
+    th = s.thermo_pressure()
+    s.close()
+    st = {"pops": OS.from_storage(p, torch.from_numpy(ghat)), "scal": torch.from_numpy(scal), "step": 0,
+          "solid": torch.from_numpy(phi < 0), "phi": torch.from_numpy(phi)}
+    for _ in range(4):
+        st, _ = OS.step(p, st)
+    fl = phi >= 0
+    assert np.abs(g_pops - oracle_ghat(p, st))[:, fl].max() < 1e-11
+    scale = np.array(p["weno_scale"][:scal.shape[0]]).reshape(-1, 1)
+    assert (np.abs(g_scal - st["scal"].numpy())[:, fl] / scale).max() < 1e-11
+    assert abs(th[0] / float(st["thermo"][0]) - 1) < 1e-13 and float(st["thermo"][0]) != 1.0
