@@ -323,14 +323,16 @@ static hipError_t build_cell_list(lbm_solver *s) {
 // One step from a.pop_in / a.scal_in, either as one instance over every cell or split into
 // the interior instance over the tile grid and the list instance over the boundary cells.
 // The split pays where the all-cell instance carries boundary code that costs the interior
-// cells occupancy: curved walls (the FULL instance; its list half is FULL) and the FP64
-// two-step step on large grids; with observables or mixture transport the step stays one
-// FULL instance.  On small grids the second launch would add a full pass of latency.  The
-// interior half writes block records [0, nblocks), the list half the records after them.
+// cells: curved walls (the FULL instance; its list half is FULL) and, on large grids, the
+// steps with transported scalars (their stencil ghost rules are most of that code); with
+// observables or mixture transport the step stays one FULL instance.  The isothermal and
+// passive steps measured slower as interior instances, and on small grids the second
+// kernel adds a pass of latency.  The interior half writes block records [0, nblocks), the
+// list half the records after them.
 static hipError_t launch_step_pass(lbm_solver *s, const StepArgs &a0) {
   StepArgs a = a0;
   a.partials = s->partials;
-  const bool split = !(a.stats || a.probe_out || a.mix) && (a.lvl || (s->NS == 6 && s->nblocks >= 4096));
+  const bool split = !(a.stats || a.probe_out || a.mix) && (a.lvl || (s->NS >= 2 && s->nblocks >= 4096));
   if (!split) {
     s->nrec = s->nblocks;
     return launch(s, LAUNCH_STEP, a);

@@ -157,6 +157,17 @@ def test_reacting_box_full_size_windows():
         _check(res, "fp32", 2)
 
 
+def test_chamber_open_full_size_windows():
+    """The 2500x500 chamber geometry with constant thermodynamic pressure (its step runs
+    split: interior instance and the listed wall and baffle cells)."""
+    params, P, u, scal, mask = L.chamber2d(closed=False)
+    full = _gpu_run(params, P, u, scal, mask.astype(np.uint8), 2)
+    for origin, size in (((0, 220, 0), (40, 60, 1)),         # burnt kernel at the left wall
+                         ((180, 190, 0), (60, 120, 1)),     # first baffle row
+                         ((2440, 440, 0), (60, 60, 1))):    # right wall, top corner
+        _check(_window(params, full, mask.astype(np.uint8), origin, size), "fp64", 2)
+
+
 def test_reacting_box_fp64_full_size_windows():
     """The reacting box in FP64: on this size the step runs split into the interior
     instance and the list instance over the inlet and outlet planes."""
