@@ -325,14 +325,15 @@ static hipError_t build_cell_list(lbm_solver *s) {
 // The split pays where the all-cell instance carries boundary code that costs the interior
 // cells: curved walls (the FULL instance; its list half is FULL) and, on large grids, the
 // steps with transported scalars (their stencil ghost rules are most of that code); with
-// observables or mixture transport the step stays one FULL instance.  The isothermal and
+// mixture transport both halves are FULL instances; with observables (statistics, probes)
+// the step stays one FULL instance.  The isothermal and
 // passive steps measured slower as interior instances, and on small grids the second
 // kernel adds a pass of latency.  The interior half writes block records [0, nblocks), the
 // list half the records after them.
 static hipError_t launch_step_pass(lbm_solver *s, const StepArgs &a0) {
   StepArgs a = a0;
   a.partials = s->partials;
-  const bool split = !(a.stats || a.probe_out || a.mix) && (a.lvl || (s->NS >= 2 && s->nblocks >= 4096));
+  const bool split = !(a.stats || a.probe_out) && (a.lvl || (s->NS >= 2 && s->nblocks >= 4096));
   if (!split) {
     s->nrec = s->nblocks;
     return launch(s, LAUNCH_STEP, a);

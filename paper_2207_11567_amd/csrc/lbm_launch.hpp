@@ -8,8 +8,8 @@ namespace lbm {
 
 // LAUNCH_STEP: every cell in one instance (FULL with curved walls, observables or mixture
 // transport); LAUNCH_STEP_INTERIOR / LAUNCH_STEP_LIST: the two halves of a split step
-// (interior cells on the tile grid, then the listed boundary cells, FULL when curved walls
-// are bound).
+// (interior cells on the tile grid, FULL with mixture transport; then the listed boundary
+// cells, FULL with curved walls or mixture transport).
 enum LaunchKind { LAUNCH_STEP = 0, LAUNCH_EXTRACT = 1, LAUNCH_INIT = 2, LAUNCH_STEP_INTERIOR = 3, LAUNCH_STEP_LIST = 4 };
 
 // Returns hipSuccess or the launch error.  nblocks covers N cells with 256 threads.
@@ -76,9 +76,9 @@ hipError_t launch_one(int kind, const StepArgs &a, int nblocks, hipStream_t st, 
     case LAUNCH_STEP:
       return full ? launch_step<Q, PREC, NS, true, MODE_ALL>(a, nblocks, st)
                   : launch_step<Q, PREC, NS, false, MODE_ALL>(a, nblocks, st);
-    case LAUNCH_STEP_INTERIOR: return launch_step<Q, PREC, NS, false, MODE_INTERIOR>(a, nblocks, st);
+    case LAUNCH_STEP_INTERIOR: return a.mix ? launch_step<Q, PREC, NS, true, MODE_INTERIOR>(a, nblocks, st) : launch_step<Q, PREC, NS, false, MODE_INTERIOR>(a, nblocks, st);
     case LAUNCH_STEP_LIST:
-      return a.lvl ? launch_step<Q, PREC, NS, true, MODE_LIST>(a, nblocks, st)
+      return (a.lvl || a.mix) ? launch_step<Q, PREC, NS, true, MODE_LIST>(a, nblocks, st)
                    : launch_step<Q, PREC, NS, false, MODE_LIST>(a, nblocks, st);
     case LAUNCH_EXTRACT:   // no collision on the extract path
       if (full)
