@@ -41,7 +41,7 @@ __device__ __forceinline__ void fwd3_vjp(R m, R z, R p, R u, R &lm, R &lz, R &lp
 
 // VJP of one inverse 1-D chimera triple (k0, k1, k2; u) -> (f-, f0, f+).
 template <class R>
-__device__ __forceinline__ void inv3_vjp(R k0, R k1, R k2, R u, R &l0, R &l1, R &l2, R &lu) {
+__device__ __forceinline__ void inv3_vjp(R k0, R k1, R /*k2: the outputs are linear in it*/, R u, R &l0, R &l1, R &l2, R &lu) {
   const R m1 = k1 + u * k0;
   const R lminus = l0, lzero = l1, lplus = l2;
   // f0 = k0 - m2, f+ = m2/2 + m1/2, f- = m2/2 - m1/2

@@ -38,10 +38,10 @@ struct lbm_solver {
   bool side_ready;
   ~lbm_solver() {
     if (side_ready) {
-      hipStreamSynchronize(side);
-      hipEventDestroy(ev_fork);
-      hipEventDestroy(ev_join);
-      hipStreamDestroy(side);
+      (void)hipStreamSynchronize(side);
+      (void)hipEventDestroy(ev_fork);
+      (void)hipEventDestroy(ev_join);
+      (void)hipStreamDestroy(side);
     }
   }
   double *stage;

@@ -48,11 +48,11 @@ hipError_t launch_surface(int Q, int prec, const StepArgs &a, int nblocks, hipSt
   const KArgs<double> k = to_kargs<double>(a);
   const double inv = 1.0 / (T_b - T_u);
   if (Q == 9) {
-    if (prec == 0) hipLaunchKernelGGL((surface_kernel<9, 0>), dim3(nblocks), dim3(256), 0, st, k, T_u, inv);
-    else hipLaunchKernelGGL((surface_kernel<9, 1>), dim3(nblocks), dim3(256), 0, st, k, T_u, inv);
+    if (prec == 0) hipLaunchKernelGGL((surface_kernel<9, 0>), dim3(nblocks), dim3(256), 0, st, k, inv);
+    else hipLaunchKernelGGL((surface_kernel<9, 1>), dim3(nblocks), dim3(256), 0, st, k, inv);
   } else {
-    if (prec == 0) hipLaunchKernelGGL((surface_kernel<27, 0>), dim3(nblocks), dim3(256), 0, st, k, T_u, inv);
-    else hipLaunchKernelGGL((surface_kernel<27, 1>), dim3(nblocks), dim3(256), 0, st, k, T_u, inv);
+    if (prec == 0) hipLaunchKernelGGL((surface_kernel<27, 0>), dim3(nblocks), dim3(256), 0, st, k, inv);
+    else hipLaunchKernelGGL((surface_kernel<27, 1>), dim3(nblocks), dim3(256), 0, st, k, inv);
   }
   return hipGetLastError();
 }

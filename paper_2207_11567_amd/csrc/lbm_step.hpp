@@ -1016,7 +1016,7 @@ static __global__ void set_thermo_kernel(double *thermo, double pi, double q, do
 // central differences with the ghost rules of grad rho (own value across walls, solids
 // and the outlet, the inlet temperature across the inlet); FP64 block records.
 template <int Q, int PREC>
-__global__ __launch_bounds__(256) void surface_kernel(KArgs<double> a, double T_u, double inv_dT) {
+__global__ __launch_bounds__(256) void surface_kernel(KArgs<double> a, double inv_dT) {
   using Sc = typename Prec<PREC>::Sc;
   using GW = typename GeomWord<Q>::T;
   constexpr int D = Lat<Q>::D;
