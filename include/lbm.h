@@ -136,7 +136,8 @@ typedef struct {
 
 /* Sizes (bytes) of the caller-provided device buffers for these parameters: one
  * population array (two are needed, A and B), one scalar array (two needed), and the
- * work buffer (geometry words, per-block FP64 partial sums, flags).
+ * work buffer (geometry words, the boundary-cell list, per-block FP64 partial sums,
+ * flags).
  * Returns LBM_E_INVALID for invalid parameters. */
 lbm_status lbm_query_sizes(const lbm_params *p, size_t *pop_bytes, size_t *scal_bytes,
                            size_t *work_bytes);
@@ -144,12 +145,16 @@ lbm_status lbm_query_sizes(const lbm_params *p, size_t *pop_bytes, size_t *scal_
 /* Validates parameters (tau0 > 1/2, F D max <= 1/(2 d) Fourier limit at rho_ref,
  * nz == 1 for D2Q9, sizes > 0, 0 <= omegas <= 2; a closed domain has no inlet or outlet
  * face and gamma > 1) and binds the buffers.  stream is a
- * hipStream_t (NULL = default stream).  scal_a/scal_b may be NULL when S == 0. */
+ * hipStream_t (NULL = default stream).  scal_a/scal_b may be NULL when S == 0.
+ * Builds the list of boundary cells (cells within two of a non-periodic face) for a
+ * split step; synchronises the stream. */
 lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_b,
                       void *scal_a, void *scal_b, void *work, lbm_solver **out);
 
 /* Solid cells (device uint8 [nz][ny][nx], nonzero = solid) for bounce-back walls and
- * zero-flux scalars; NULL clears the geometry.  The mask is read once here. */
+ * zero-flux scalars; NULL clears the geometry.  The mask is read once here; the list of
+ * boundary cells (solid, or a solid within their links or +-2 stencil, or near a
+ * non-periodic face) is rebuilt on the host.  Synchronises the stream. */
 lbm_status lbm_set_geometry(lbm_solver *s, const uint8_t *solid_dev);
 
 /* Curved walls (the paper's treatment of curved boundaries for both solvers, Sec. 1 and
@@ -165,7 +170,9 @@ lbm_status lbm_set_geometry(lbm_solver *s, const uint8_t *solid_dev);
  * the first node takes the even quadratic through the two nearest nodes), the density
  * there is the ideal gas of those values, and diffusion fluxes through solid faces stay
  * zero.  Domain faces keep the halfway rules.  The library keeps phi_dev (the caller keeps
- * it alive until the next geometry call); NULL clears the geometry. */
+ * it alive until the next geometry call); NULL clears the geometry.  The boundary-cell
+ * list is rebuilt as for lbm_set_geometry; steps then run split, the boundary cells in
+ * the curved-wall kernel and the others in the interior kernel.  Synchronises. */
 lbm_status lbm_set_wall_distance(lbm_solver *s, const double *phi_dev);
 
 /* Equilibrium initialisation (Eq. 6): post-collision populations of level -1 are set to

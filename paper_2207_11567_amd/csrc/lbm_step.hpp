@@ -357,7 +357,10 @@ __device__ __forceinline__ double w_over_T(const ThermoT<R> &t, const R (&v)[NS 
 // with mixture-averaged transport).
 template <int Q, int PREC, int NS, bool EXTRACT, bool FULL, int COLL, int MODE>
 constexpr int step_waves_per_eu() {
-  return (Q == 27 && PREC != 0 && NS == 6 && !EXTRACT && (!FULL || MODE == MODE_INTERIOR) && COLL == COLL_CUM1 && MODE != MODE_LIST) ? 4 : 1;
+  return (Q == 27 && PREC != 0 && NS == 6 && !EXTRACT && COLL == COLL_CUM1 && MODE != MODE_LIST &&
+          (!FULL || MODE == MODE_INTERIOR))
+             ? 4
+             : 1;
 }
 template <int Q, int PREC, int NS, bool EXTRACT, bool FULL, int COLL, int MODE>
 __global__ __launch_bounds__(256)
