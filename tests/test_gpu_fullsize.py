@@ -168,6 +168,20 @@ def test_chamber_open_full_size_windows():
         _check(_window(params, full, mask.astype(np.uint8), origin, size), "fp64", 2)
 
 
+def test_reacting_box_fp16_storage_full_size_windows():
+    """The reacting box with FP16 population storage (split step: the interior instance at
+    four waves per SIMD and the boundary list), one step: half an FP16 ulp of each output
+    plus the FP32 bounds."""
+    params, P, u, scal = L.reacting_box()
+    params["precision"] = "fp16s"
+    full = _gpu_run(params, P, u, scal, None, 1)
+    for origin, size in (((50, 60, 0), (12, 12, 10)), ((90, 100, 184), (12, 12, 16)),
+                         ((180, 3, 374), (12, 12, 10))):
+        res = _window(params, full, None, origin, size)
+        assert res["pop_beyond_half_fp16_ulp"] <= 2e-7, res
+        assert res["scal_rel"] <= 2e-6, res
+
+
 def test_reacting_box_fp64_full_size_windows():
     """The reacting box in FP64: on this size the step runs split into the interior
     instance and the list instance over the inlet and outlet planes."""
