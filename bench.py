@@ -175,16 +175,32 @@ def cpu_baseline(name, budget_s=15.0):
                        torch.from_numpy(solid).bool() if solid is not None else None)
     N = p["nx"] * p["ny"] * p["nz"]
     OS.step(p, st)
-    t0 = time.time()
-    n = 0
-    while n < 2 or time.time() - t0 < budget_s:
-        st, _ = OS.step(p, st)
-        n += 1
-        if n >= 200:
-            break
-    dt = time.time() - t0
-    return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
-            "kind": "oracle", "sample": f"{sample}: {N} cells x {n} steps in {dt:.1f} s (FP64)"}
+
+    def timed(budget):
+        nonlocal st
+        t0 = time.time()
+        n = 0
+        while n < 2 or time.time() - t0 < budget:
+            st, _ = OS.step(p, st)
+            n += 1
+            if n >= 200:
+                break
+        return n, time.time() - t0
+
+    n, dt = timed(budget_s)
+    threads = torch.get_num_threads()
+    torch.set_num_threads(1)                   # the same oracle on one host thread
+    n1, dt1 = timed(budget_s / 3)
+    torch.set_num_threads(threads)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "sample": f"{sample}: {N} cells x {n} steps in {dt:.1f} s (FP64)",
+            "single_thread_value": N * n1 / dt1 / 1e6, "host_cpu": model}
 
 
 def traffic_for(name, p, bpc, N):
