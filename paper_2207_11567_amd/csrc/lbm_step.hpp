@@ -880,34 +880,42 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         const R ugr = u[0] * gradrho[0] + u[1] * gradrho[1] + u[2] * gradrho[2];
         const R rsL = rho0 * s * Lam;
         // Eq. 2: Xi_i = cs2 (f_eq/rho - w)(c - u).grad rho + w rho cs2 Lambda, formed once
-        // per population and kept for the post-collision form (Eq. 8)
-        auto xi_of = [&](int i) -> R {
-          if constexpr (NS >= 2) {
-            const R cu = R(cx(i)) * u[0] + R(cy(i)) * u[1] + (D == 3 ? R(cz(i)) * u[2] : R(0));
-            const R cg = R(cx(i)) * gradrho[0] + R(cy(i)) * gradrho[1] + (D == 3 ? R(cz(i)) * gradrho[2] : R(0));
-            const R wi = R(wgt<Q>(i));
-            return s * wi * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu) * (cg - ugr) + wi * rsL;
-          } else {
-            return R(0);
-          }
-        };
+        // per population and kept for the post-collision form (Eq. 8), here already over
+        // 2 rho cs2 (the factor of Eq. 13).  Opposite velocities share c.u and c.grad rho up
+        // to sign: with a = c.u, b = c.grad rho, f_eq/rho - w = w (3a + 4.5a^2 - 1.5u.u), so
+        // each pair needs one square and the two signs of the odd parts.
+        R Xh[NS >= 2 ? Q : 1];
         R e[Q];
-        R Xi[NS >= 2 ? Q : 1];
         R Es = R(0);
         // sum_i Xi_i = cs2 (rho Lambda + u . grad rho) (the moments of Eq. 2)
         const R Xs = NS >= 2 ? s * (rho0 * Lam + ugr) : R(0);
-        const R half_rcs = R(1.5) * irho0;               // 1/(2 rho cs2)
+        if constexpr (NS >= 2) {
+          const R k1 = R(0.5) * irho0;                   // cs2 / (2 rho cs2)
+          const R k0 = R(0.5) * Lam;                     // rho cs2 Lambda / (2 rho cs2)
+          const R e0 = R(-1.5) * uu;
+#pragma unroll
+          for (int i = 0; i < Q / 2; ++i) {
+            const int o = Q - 1 - i;
+            R a0 = R(0), b0 = R(0);
+            if (cx(i)) { a0 += R(cx(i)) * u[0]; b0 += R(cx(i)) * gradrho[0]; }
+            if (cy(i)) { a0 += R(cy(i)) * u[1]; b0 += R(cy(i)) * gradrho[1]; }
+            if (D == 3 && cz(i)) { a0 += R(cz(i)) * u[2]; b0 += R(cz(i)) * gradrho[2]; }
+            const R ev = R(4.5) * a0 * a0 + e0, od = R(3) * a0;
+            const R wk1 = R(wgt<Q>(i)) * k1, wk0 = R(wgt<Q>(i)) * k0;
+            Xh[i] = wk1 * ((ev + od) * (b0 - ugr)) + wk0;
+            Xh[o] = wk1 * ((ev - od) * (-b0 - ugr)) + wk0;
+          }
+          constexpr int c0 = Q / 2;
+          Xh[c0] = R(wgt<Q>(c0)) * (k1 * (e0 * -ugr) + k0);
+        }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          if constexpr (NS >= 2) {
-            const R xi = xi_of(i);
-            Xi[i] = xi;
-            e[i] = r * gh[i] + xi * half_rcs;            // Eq. 13 minus the weights
-          } else {
-            e[i] = gh[i];                                // rho = rho_ref, Xi = 0
-          }
-          Es += e[i];
+          if constexpr (NS >= 2) e[i] = r * gh[i] + Xh[i];   // Eq. 13 minus the weights
+          else e[i] = gh[i];                                  // rho = rho_ref, Xi = 0
         }
+        // sum_i e_i from the moments: r sum ghat + sum Xi / (2 rho cs2)
+        if constexpr (NS >= 2) Es = r * sg + Xs * (R(1.5) * irho0);
+        else Es = sg;
 #pragma unroll
         for (int i = 0; i < Q; ++i) e[i] -= R(wgt<Q>(i)) * Es;   // d = f~ - w
         R nu = viscosity_irho(a.th, irho0);
@@ -929,7 +937,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
 #pragma unroll
           for (int i = 0; i < Q; ++i) {
             R gs;
-            if constexpr (NS >= 2) gs = R(wgt<Q>(i)) * base + e[i] * invr + Xi[i] * hP0;   // Eq. 8
+            if constexpr (NS >= 2) gs = R(wgt<Q>(i)) * base + (e[i] + Xh[i]) * invr;   // Eq. 8
             else gs = R(wgt<Q>(i)) * base + e[i];
             bst<St, 2>(slice(pout + (size_t)i * N), un, encode<St>(gs));
           }
@@ -943,7 +951,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             const R cu = R(cx(i)) * u[0] + R(cy(i)) * u[1] + (D == 3 ? R(cz(i)) * u[2] : R(0));
             const R geq = R(wgt<Q>(i)) * (ph1 + kq * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
             R xh = R(0);
-            if constexpr (NS >= 2) xh = Xi[i] * hP0;
+            if constexpr (NS >= 2) xh = Xh[i] * invr;
             const R gp = gh[i] + xh;
             bst<St, 2>(slice(pout + (size_t)i * N), un, encode<St>(gp - om * (gp - geq) + xh));
           }
