@@ -231,6 +231,8 @@ static StepArgs make_args(const lbm_solver *s) {
   a.collision = p.collision;
   a.gal = p.galilean;
   a.remap = 1;
+  // population copies larger than the 256 MB Infinity Cache: cached pull loads
+  a.pull_cached = (size_t)s->Q * (size_t)s->N * pop_elem(s->prec) > ((size_t)256 << 20);
   a.band_rows = 0;
   if (p.nx % 64 == 0 && p.ny % 4 == 0)
     for (int b : {32, 16, 8, 4})

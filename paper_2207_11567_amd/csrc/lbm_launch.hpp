@@ -50,6 +50,13 @@ hipError_t launch_step(const StepArgs &a, int nblocks, hipStream_t st) {
   using R = typename Prec<PREC>::R;
   switch (collision_instance<Q, PREC>(a)) {
     case COLL_CUM1:
+      // the plain production instances also come with cached pull loads (large grids)
+      if constexpr (!FULL && MODE != MODE_LIST)
+        if (a.pull_cached) {
+          hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, false, COLL_CUM1, MODE, true>), dim3(nblocks), dim3(256),
+                             0, st, to_kargs<R>(a));
+          break;
+        }
       hipLaunchKernelGGL((step_kernel<Q, PREC, NS, false, FULL, COLL_CUM1, MODE>), dim3(nblocks), dim3(256), 0, st,
                          to_kargs<R>(a));
       break;

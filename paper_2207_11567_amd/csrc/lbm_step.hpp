@@ -72,6 +72,7 @@ struct StepArgs {
   int gal;             // Galilean correction of the cumulant collision
   int remap;           // XCD-aware block order
   int band_rows;       // 0: linear 256-cell tiles; else 64x4 tiles in bands of this many rows
+  int pull_cached;     // production instance with cached pull loads (else streaming loads)
   double P0;           // rho_ref cs2
   double wb, wh, smag18;
   double inlet_u[3], inlet_noise, outlet_P;
@@ -362,7 +363,7 @@ constexpr int step_waves_per_eu() {
              ? 4
              : 1;
 }
-template <int Q, int PREC, int NS, bool EXTRACT, bool FULL, int COLL, int MODE>
+template <int Q, int PREC, int NS, bool EXTRACT, bool FULL, int COLL, int MODE, bool PULLC = false>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<Q, PREC, NS, EXTRACT, FULL, COLL, MODE>())))
 void step_kernel(KArgs<typename Prec<PREC>::R> a) {
@@ -531,10 +532,17 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
                           (D == 3 && (code[2][1] >= 0 || code[2][3] >= 0));
       constexpr GW linkmask = (GW(1) << Q) - GW(1);
       if (MODE == MODE_INTERIOR || (!border && !(gw & linkmask))) {
+        // PULLC (grids larger than the Infinity Cache): ordinary cached loads.  A wave's 64
+        // shifted values of a population with c_x != 0 straddle a cache line that the
+        // neighbouring tile in x reads too, and with streaming loads that line was often
+        // gone again (256^3 FP32 step: 0.688 -> 0.656 ms, HBM reads 1.08 -> 1.00 of the
+        // algorithmic ones).  Grids that fit keep streaming loads, which leave the cache
+        // to the freshly written populations the next step reads (cached: 4-12 % slower).
+        constexpr int PULL_AUX = PULLC ? 0 : 2;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const unsigned m = un + (unsigned)(off[0][2 - cx(i)] + off[1][2 - cy(i)] + (D == 3 ? off[2][2 - cz(i)] : 0));
-          gh[i] = decode<R>(bld<St, 2>(slice(pin + (size_t)i * N), m));
+          gh[i] = decode<R>(bld<St, PULL_AUX>(slice(pin + (size_t)i * N), m));
         }
       } else if constexpr (MODE != MODE_INTERIOR) {
         // boundary cell: bounce-back, moving-wall inlet, anti-bounce-back outlet
