@@ -211,3 +211,35 @@ def test_reacting_box_cone_curved_walls_full_size_windows():
     for origin, size in (((52, 90, 12), (14, 12, 10)),        # base rim
                          ((90, 90, 70), (12, 12, 12))):       # apex
         _check(_window(params, full, phi, origin, size), "fp32", 2)
+
+
+@pytest.mark.parametrize("phys,prec,n,reps", [
+    ("isothermal", "fp64", (96, 96, 96), (2, 2, 2)),
+    ("isothermal", "fp32", (96, 96, 96), (2, 2, 2)),
+    ("isothermal", "fp16s", (96, 96, 96), (2, 2, 2)),
+    ("two_step", "fp32", (128, 128, 128), (1, 2, 2))])
+def test_large_grid_instances_match_a_tiled_small_grid(phys, prec, n, reps):
+    """A periodic box tiled along its axes evolves exactly as the box itself: every output
+    of a cell depends only on its neighbours, which hold the same values in both grids.
+    The tiled grid's population copy exceeds 256 MB, so it runs the cached-pull instance,
+    the box the streaming one, each with its own tile order; both run the same kernel
+    otherwise (with two-step scalars both grids are large enough for the split step's
+    interior instance), so after three steps they must agree bit for bit."""
+    from tests.gpu_helpers import fetch, gpu_state, make_solver, random_state
+    from tests.test_gpu_parity import _params
+    steps = 3
+    small = _params("D3Q27", n, phys, "cumulant", precision=prec, omega_high=1.0)
+    big = dict(small, nz=reps[0] * n[0], ny=reps[1] * n[1], nx=reps[2] * n[2])
+    ghat, scal = random_state(small, 23)
+    out = []
+    for params, r in ((small, (1, 1, 1, 1)), (big, (1,) + reps)):
+        print(f"tiled-box case: {phys} {prec} {params['nz']}x{params['ny']}x{params['nx']}", flush=True)
+        s = make_solver(params)
+        gpu_state(s, np.tile(ghat, r), np.tile(scal, r))
+        s.step(steps)
+        out.append(fetch(s))
+        s.close()
+    (p0, s0, k0), (p1, s1, k1) = out
+    assert k0 == k1 == steps
+    assert np.array_equal(np.tile(p0, (1,) + reps), p1)
+    assert np.array_equal(np.tile(s0, (1,) + reps), s1)
