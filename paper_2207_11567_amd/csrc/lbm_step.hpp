@@ -668,13 +668,17 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             const unsigned mp2 = un + (unsigned)off[d][4], mm2 = un + (unsigned)off[d][0];
             const R ud = u[d];
             const bool up = ud >= R(0);
+            // FAST: vp1 holds the downwind neighbour and vm1 the upwind one (addresses
+            // chosen once per axis instead of values per scalar); diffusion and density are
+            // symmetric in the two, grad rho takes the sign back
+            const unsigned mdw = up ? mp1 : mm1, muw = up ? mm1 : mp1;
             R vp1[NSV], vm1[NSV];
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
               const Sc *sq = sin_ + (size_t)q * N;
               if (FAST) {
-                vp1[q] = (R)bld<Sc>(slice(sq), mp1);
-                vm1[q] = (R)bld<Sc>(slice(sq), mm1);
+                vp1[q] = (R)bld<Sc>(slice(sq), mdw);
+                vm1[q] = (R)bld<Sc>(slice(sq), muw);
               } else {
                 vp1[q] = sp1 == ST_FLUID ? (R)bld<Sc>(slice(sq), mp1) : sp1 == ST_INLET ? phin[q] : phi0[q];
                 vm1[q] = sm1 == ST_FLUID ? (R)bld<Sc>(slice(sq), mm1) : sm1 == ST_INLET ? phin[q] : phi0[q];
@@ -725,6 +729,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             else if (sm1 == ST_INLET) rm = rho_in;
             else if (c1m) rm = density<NS, R>(a.th, vm1, pim);
             gradrho[d] = R(0.5) * (rp - rm);
+            if (FAST && !up) gradrho[d] = -gradrho[d];
             // face coefficients: arithmetic mean of rho D (uniform when rho nu is constant)
             R cfp, cfm;
             if (FAST) {
@@ -767,8 +772,8 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
                   else if (c3p) vp2 = lerp(vp1[q], v0, w3p);
                   vU2 = up ? vm2 : vp2;
                 }
-                const R vU1 = up ? vm1[q] : vp1[q];
-                const R vD1 = up ? vp1[q] : vm1[q];
+                const R vU1 = FAST || up ? vm1[q] : vp1[q];
+                const R vD1 = FAST || up ? vp1[q] : vm1[q];
                 adv[q] += au * weno3_diff(vU2, vU1, v0, vD1, a.eps[q]);
               }
             }
@@ -889,17 +894,20 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         const R rsL = rho0 * s * Lam;
         // Eq. 2: Xi_i = cs2 (f_eq/rho - w)(c - u).grad rho + w rho cs2 Lambda, formed once
         // per population and kept for the post-collision form (Eq. 8), here already over
-        // 2 rho cs2 (the factor of Eq. 13).  Opposite velocities share c.u and c.grad rho up
-        // to sign: with a = c.u, b = c.grad rho, f_eq/rho - w = w (3a + 4.5a^2 - 1.5u.u), so
-        // each pair needs one square and the two signs of the odd parts.
+        // 2 rho cs2 (the factor of Eq. 13) and less w_i Es (below).  Opposite velocities
+        // share c.u and c.grad rho up to sign: with a = c.u, b = c.grad rho,
+        // f_eq/rho - w = w (3a + 4.5a^2 - 1.5u.u), so each pair needs one square and the two
+        // signs of the odd parts.
         R Xh[NS >= 2 ? Q : 1];
         R e[Q];
-        R Es = R(0);
         // sum_i Xi_i = cs2 (rho Lambda + u . grad rho) (the moments of Eq. 2)
         const R Xs = NS >= 2 ? s * (rho0 * Lam + ugr) : R(0);
+        // Es = sum_i of the pre-conditioned populations minus the weights (Eq. 13), from the
+        // moments: r sum ghat + sum Xi / (2 rho cs2); d = f~ - w = e - w Es has zero sum
+        const R Es = NS >= 2 ? r * sg + Xs * (R(1.5) * irho0) : sg;
         if constexpr (NS >= 2) {
           const R k1 = R(0.5) * irho0;                   // cs2 / (2 rho cs2)
-          const R k0 = R(0.5) * Lam;                     // rho cs2 Lambda / (2 rho cs2)
+          const R k0 = R(0.5) * Lam - Es;                // rho cs2 Lambda / (2 rho cs2) - Es
           const R e0 = R(-1.5) * uu;
 #pragma unroll
           for (int i = 0; i < Q / 2; ++i) {
@@ -918,14 +926,9 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          if constexpr (NS >= 2) e[i] = r * gh[i] + Xh[i];   // Eq. 13 minus the weights
-          else e[i] = gh[i];                                  // rho = rho_ref, Xi = 0
+          if constexpr (NS >= 2) e[i] = r * gh[i] + Xh[i];          // d = f~ - w (Eq. 13)
+          else e[i] = gh[i] - R(wgt<Q>(i)) * Es;                     // rho = rho_ref, Xi = 0
         }
-        // sum_i e_i from the moments: r sum ghat + sum Xi / (2 rho cs2)
-        if constexpr (NS >= 2) Es = r * sg + Xs * (R(1.5) * irho0);
-        else Es = sg;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) e[i] -= R(wgt<Q>(i)) * Es;   // d = f~ - w
         R nu = viscosity_irho(a.th, irho0);
         if constexpr (FULL && NS == 6) {
           if (a.mx.on) nu = mu_c * irho0;
@@ -939,13 +942,14 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         const R hP0 = R(0.5) * a.invP0;
         const R base = sg + Xs * hP0;                    // (1/r) m0 - 1
         const R invr = rho0 * a.invP0 * s;              // rho/rho_ref = rho cs2/P0
+        const R baseE = NS >= 2 ? base + Es * invr : base;   // with the w_i Es taken from Xh
         if constexpr (COLL != COLL_BGK) {
           if constexpr (Q == 9) collide_d2q9(e, u[0], u[1], rt);
           else collide_d3q27<R, COLL == COLL_CUM1>(e, u[0], u[1], u[2], rt);
 #pragma unroll
           for (int i = 0; i < Q; ++i) {
             R gs;
-            if constexpr (NS >= 2) gs = R(wgt<Q>(i)) * base + (e[i] + Xh[i]) * invr;   // Eq. 8
+            if constexpr (NS >= 2) gs = R(wgt<Q>(i)) * baseE + (e[i] + Xh[i]) * invr;   // Eq. 8
             else gs = R(wgt<Q>(i)) * base + e[i];
             bst<St, 2>(slice(pout + (size_t)i * N), un, encode<St>(gs));
           }
@@ -959,7 +963,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             const R cu = R(cx(i)) * u[0] + R(cy(i)) * u[1] + (D == 3 ? R(cz(i)) * u[2] : R(0));
             const R geq = R(wgt<Q>(i)) * (ph1 + kq * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
             R xh = R(0);
-            if constexpr (NS >= 2) xh = Xh[i] * invr;
+            if constexpr (NS >= 2) xh = (Xh[i] + R(wgt<Q>(i)) * Es) * invr;
             const R gp = gh[i] + xh;
             bst<St, 2>(slice(pout + (size_t)i * N), un, encode<St>(gp - om * (gp - geq) + xh));
           }
