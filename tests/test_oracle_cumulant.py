@@ -172,3 +172,45 @@ def test_smagorinsky_closed_form(name):
     k_in = ((c[:, 0, None] - u[0]) * (c[:, 1, None] - u[1]) * f_t).sum(0)
     k_out = ((c[:, 0, None] - u[0]) * (c[:, 1, None] - u[1]) * fo).sum(0)
     assert torch.allclose(k_out, (1 - om) * k_in, atol=1e-16, rtol=0)
+
+
+@pytest.mark.parametrize("name", LATS)
+def test_relaxation_at_intermediate_rates(name):
+    """One collision at rates strictly between 0 and 1 (shear 0.3, bulk 0.45, order >= 3
+    0.6), cumulants of input and output from the independent brute force above: every
+    cumulant of order >= 3 comes out scaled by exactly 1 - omega_high, the off-diagonal and
+    deviatoric second-order ones by 1 - omega_s, the trace's distance from D cs2 by
+    1 - omega_bulk, and the mean is untouched (rates 0 and 1 alone cannot tell 1 - w from,
+    say, (1 - w)^2)."""
+    lat = get(name)
+    c = velocities(lat.Q)
+    n = 8
+    fp = _random_fprime(lat, n, 11, amp=0.05)
+    u = _velocity(lat, fp)
+    ws, wb, wh = 0.3, 0.45, 0.6
+    out, _ = C.cumulant_collide(lat, fp, u, 0.01, 0.0, wb, wh,
+                                omega_s=torch.full((n,), ws, dtype=torch.float64))
+    m0 = fp.sum(0)
+    D = lat.D
+    diag = [tuple(2 if k == d else 0 for k in range(D)) for d in range(D)]
+    for j in range(n):
+        f_in = (fp[:, j] - lat.w * (m0[j] - 1)).numpy()
+        f_out = (out[:, j] - lat.w * (m0[j] - 1)).numpy()
+        assert abs(f_in.sum() - 1) < 1e-14 and abs(f_out.sum() - 1) < 1e-14
+        ci, co = mgf_cumulants(f_in, c), mgf_cumulants(f_out, c)
+        checked = 0
+        for e in ci:
+            order = sum(e)
+            if order == 1:
+                assert abs(co[e] - ci[e]) < 1e-15
+            elif order >= 3:
+                assert abs(co[e] - (1 - wh) * ci[e]) < 1e-14, (e, co[e], ci[e])
+                checked += abs(ci[e]) > 1e-9              # the input really has them
+            elif order == 2 and e not in diag:
+                assert abs(co[e] - (1 - ws) * ci[e]) < 1e-15
+        tr_in = sum(ci[e] for e in diag)
+        tr_out = sum(co[e] for e in diag)
+        assert abs((tr_out - D * CS2) - (1 - wb) * (tr_in - D * CS2)) < 1e-15
+        for e in diag:
+            assert abs((co[e] - tr_out / D) - (1 - ws) * (ci[e] - tr_in / D)) < 1e-15
+        assert checked == (3 if D == 2 else 17)
