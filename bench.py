@@ -1,13 +1,14 @@
 """Throughput of the hybrid low-Mach LB/FD time step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload reacting_box] [--no-cpu]
-                [--no-extra] [--kernel-only]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--repeats R] [--workload reacting_box]
+                [--no-cpu] [--no-extra] [--kernel-only]
 
 Prints one JSON line.  A step is one pass of the whole hot path over the grid: pull
 streaming with boundary conditions, scalar stencils and chemistry, moments, source,
 cumulant collision, the finite-difference scalar update and the FP64 block sums.
 value = lattice updates per second (MLUPS) with every buffer resident in HBM; timed with
-HIP events on the stream the kernels run on.  The roofline figure uses the algorithmic
+HIP events on the stream the kernels run on, R regions of K steps (default 3), the step
+time being the median of the regions' means.  The roofline figure uses the algorithmic
 bytes of one launch (2 Q s_pop + 2 S s_scal + geometry word + block partials, per cell)
 over the average launch duration.  The CPU baseline times the FP64 oracle on a bounded
 sample of the same workload on the host cores.
@@ -95,7 +96,7 @@ def bytes_per_cell(p):
     return 2 * Q * sp + 2 * NS * ss + 64.0 / 256.0
 
 
-def run_gpu(name, steps, warmup, precision=None, observables=False):
+def run_gpu(name, steps, warmup, precision=None, observables=False, repeats=3):
     import torch
 
     from paper_2207_11567_amd import Solver
@@ -116,16 +117,22 @@ def run_gpu(name, steps, warmup, precision=None, observables=False):
         # running statistics at every level and 8 probes along the mid-line
         solver.set_statistics(1)
         cells = [int(p["nx"] * (k + 1) / 9) + p["nx"] * (p["ny"] // 2) for k in range(8)]
-        solver.set_probes(cells, capacity=steps + warmup)
+        solver.set_probes(cells, capacity=warmup + steps * max(1, repeats))
     solver.step(warmup)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(solver.stream)
-    solver.step(steps)
-    e1.record(solver.stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    # `repeats` timed regions of `steps` steps each, every one bracketed by device
+    # synchronisation; the step time is the median of the regions' means
+    rep_ms = []
+    for _ in range(max(1, repeats)):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(solver.stream)
+        solver.step(steps)
+        e1.record(solver.stream)
+        torch.cuda.synchronize()
+        rep_ms.append(e0.elapsed_time(e1) / steps)
+    ms = float(np.median(rep_ms)) * steps
     sums = solver.step_sums()            # raises on a non-finite value
     if p["physics"] in ("one_step", "two_step"):
         T_u, T_b = (p["chem"][2], p["chem"][3]) if p["physics"] == "one_step" else (p["inlet_T"], 1950.0)
@@ -147,7 +154,8 @@ def run_gpu(name, steps, warmup, precision=None, observables=False):
     return {"workload": name, "desc": desc, "params": p, "cells": N, "steps": steps,
             "ms_per_step": ms / steps, "mlups": N * steps / (ms / 1e3) / 1e6,
             "fluid_mlups": n_fluid * steps / (ms / 1e3) / 1e6,
-            "bytes_per_cell": bpc, "achieved_gbs": achieved, "sums": sums, "observables": extra}
+            "bytes_per_cell": bpc, "achieved_gbs": achieved, "sums": sums, "observables": extra,
+            "repeat_ms_per_step": [round(v, 5) for v in rep_ms]}
 
 
 def cpu_baseline(name, budget_s=15.0):
@@ -387,6 +395,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--repeats", type=int, default=3,
+                    help="timed regions of --steps steps each; ms_per_step is their median")
     ap.add_argument("--workload", default="reacting_box",
                     choices=["reacting_box", "flame2d", "hit", "tgv", "passive_box", "chamber2d",
                              "chamber2d_open", "reacting_box_mixture", "reacting_box_cone"])
@@ -421,7 +431,8 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    main_res = run_gpu(args.workload, args.steps, args.warmup, args.precision, args.observables)
+    main_res = run_gpu(args.workload, args.steps, args.warmup, args.precision, args.observables,
+                       repeats=args.repeats)
     p = main_res["params"]
     N = main_res["cells"]
     print(f"# {args.workload}: {main_res['mlups']:.1f} MLUPS, {main_res['ms_per_step']:.3f} ms/step",
@@ -476,6 +487,11 @@ def main():
         "config": {"workload": main_res["desc"], "nx": p["nx"], "ny": p["ny"], "nz": p["nz"],
                    "lattice": p["lattice"], "precision": p["precision"], "physics": p["physics"],
                    "parallelism": "single GPU"},
+        "timing": {"repeats": len(main_res["repeat_ms_per_step"]),
+                   "ms_per_step_each": main_res["repeat_ms_per_step"],
+                   "ms_per_step_min": min(main_res["repeat_ms_per_step"]),
+                   "ms_per_step_max": max(main_res["repeat_ms_per_step"]),
+                   "ms_per_step_is": "median over the repeats"},
         "roofline": roofline, "cpu_baseline": cpu,
         "paper_context": {"value": 0.4, "unit": "MLUPS", "hardware": "SuperMUC-NG CPU cluster",
                           "note": "LB + FD + thermochemistry on PRECCINSTA (about 30 Mi points); "

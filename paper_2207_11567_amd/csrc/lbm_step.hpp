@@ -112,6 +112,7 @@ template <class R> struct KArgs {
   R phi_in[8], eps[8];
   unsigned long long seed;
   double inv_T_ref_d, W_d[6];
+  double P0d;          // P0 in FP64 (field outputs and sums of P_h)
   ThermoT<R> th;
   MixT<R> mx;
 };
@@ -136,6 +137,7 @@ template <class R> KArgs<R> to_kargs(const StepArgs &a) {
   k.seed = a.seed;
   const double *ch = a.th.chem;
   k.inv_T_ref_d = 1.0 / a.th.T_ref;
+  k.P0d = a.P0;
   for (int q = 0; q < 6; ++q) k.W_d[q] = ch[5 + q] > 0.0 ? ch[5 + q] : 1.0;
   ThermoT<R> &t = k.th;
   t.rho_ref = (R)a.th.rho_ref; t.nu_ref = (R)a.th.nu_ref; t.mu_ref = (R)(a.th.nu_ref * a.th.rho_ref);
@@ -844,10 +846,14 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
           if (a.thermo) Lam -= qn;                        // div u = Lambda - dln(pi)/dt
         }
       }
-      const R Ph = P0 * (sg + R(1)) + R(0.5) * rho0 * s * Lam;   // Eq. 7a
+      // Eq. 7a: P_h = P0 (1 + sum ghat) + (dt/2) rho cs2 Lambda, formed in FP64 from the
+      // deviation sum (1 + sum ghat in the compute precision would round away the pressure
+      // fluctuation's last digits, and P0 in it is rounded too)
+      const R hLam = R(0.5) * rho0 * s * Lam;
+      const double Ph = a.P0d * (1.0 + (double)sg) + (double)hLam;
 
       if (EXTRACT) {
-        if (a.f_P) a.f_P[n] = (double)Ph;
+        if (a.f_P) a.f_P[n] = Ph;
         if (a.f_rho) a.f_rho[n] = (double)rho0;
         if (a.f_u)
 #pragma unroll
@@ -860,7 +866,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         // running mean and squared-deviation sums (Welford) of u and P_h - P0 at sampled
         // levels; probe rows (u, P_h) at the probe cells
         if (FULL && a.stats) {
-          const double x[4] = {(double)u[0], (double)u[1], (double)u[2], (double)Ph - (double)a.P0};
+          const double x[4] = {(double)u[0], (double)u[1], (double)u[2], Ph - a.P0d};
 #pragma unroll
           for (int j = 0; j <= D; ++j) {
             const double xv = x[j == D ? 3 : j];
@@ -876,7 +882,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             if (n == a.probe[j]) {
 #pragma unroll
               for (int d = 0; d < D; ++d) a.probe_out[j * (D + 1) + d] = (double)u[d];
-              a.probe_out[j * (D + 1) + D] = (double)Ph;
+              a.probe_out[j * (D + 1) + D] = Ph;
             }
         }
         // ------------------------------------------------------------ scalar update
@@ -962,7 +968,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         } else {
           // BGK in the pre-conditioned frame (Eq. 5 with the half-source split)
           const R om = shear_rate(rt, pipi_of<Q, R>(e, u));
-          const R ph1 = Ph * a.invP0 - R(1);
+          const R ph1 = sg + hLam * a.invP0;
           const R kq = rho0 * s * a.invP0;
 #pragma unroll
           for (int i = 0; i < Q; ++i) {
@@ -974,13 +980,13 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             bst<St, 2>(slice(pout + (size_t)i * N), un, encode<St>(gp - om * (gp - geq) + xh));
           }
         }
-        if (!isfinite(chk + Ph + u[0] + u[1] + u[2])) atomicOr(a.flag, 1);
+        if (!isfinite(chk + sg + hLam + u[0] + u[1] + u[2])) atomicOr(a.flag, 1);
       }
 
       // ---------------------------------------------------------------- FP64 sums
       // (cell values in the compute precision, accumulated in FP64)
       red[0] = (double)rho0;
-      red[1] = (double)Ph;
+      red[1] = Ph;
       red[2] = (double)(rho0 * u[0]);
       red[3] = (double)(rho0 * u[1]);
       red[4] = (double)(rho0 * u[2]);

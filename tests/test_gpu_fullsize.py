@@ -34,9 +34,9 @@ def _gpu_run(params, P, u, scal, mask, steps):
     return out + [P, u, scal, steps]
 
 
-def _window(params, full, mask, origin, size):
-    """Oracle run of a window from the workload's fields; returns the largest GPU-vs-oracle
-    differences."""
+def _window(params, full, mask, origin, size, state=None):
+    """Oracle run of a window from the workload's fields (or, with state = (ghat, scal), from
+    that stored host state); returns the largest GPU-vs-oracle differences."""
     p1, s1, P, u, scal, steps = full
     HALO = 3 * steps
     dims = [params["nx"], params["ny"], params["nz"]]
@@ -81,12 +81,20 @@ def _window(params, full, mask, origin, size):
     # the window's inputs: equilibrium from the FP64 fields, then stored (scalars and
     # populations rounded to the storage precision as the GPU stores them)
     sc_w = None if scal is None else np.ascontiguousarray(scal[(slice(None),) + sel])
-    st = OS.init_state(wp, torch.from_numpy(np.ascontiguousarray(P[sel])),
-                       torch.from_numpy(np.ascontiguousarray(u[(slice(None),) + sel])),
-                       None if sc_w is None else torch.from_numpy(sc_w), solid, phi)
-    if sc_w is not None:
+    if state is not None:
+        gh, sc = state
+        shape = (len(idx[2]), len(idx[1]), len(idx[0]))
+        st = {"pops": OS.from_storage(wp, torch.from_numpy(np.ascontiguousarray(gh[(slice(None),) + sel]).astype(np.float64))),
+              "scal": (torch.zeros((0,) + shape, dtype=torch.float64) if sc is None else
+                       torch.from_numpy(np.ascontiguousarray(sc[(slice(None),) + sel]).astype(np.float64))),
+              "step": 0, "solid": torch.zeros(shape, dtype=torch.bool) if solid is None else solid}
+    else:
+        st = OS.init_state(wp, torch.from_numpy(np.ascontiguousarray(P[sel])),
+                           torch.from_numpy(np.ascontiguousarray(u[(slice(None),) + sel])),
+                           None if sc_w is None else torch.from_numpy(sc_w), solid, phi)
+    if sc_w is not None and state is None:
         st["scal"] = torch.from_numpy(sc_w.astype(SCAL_NP[params["precision"]]).astype(np.float64))
-    if params["precision"] != "fp64":
+    if params["precision"] != "fp64" and state is None:
         # populations enter storage once at initialisation, rounded once (numpy converts
         # FP64 to FP16 in one rounding, as the device does; a detour through FP32 would not)
         gh = OS.to_storage(wp, st["pops"]).numpy().astype(STORE_NP[params["precision"]])
@@ -100,15 +108,46 @@ def _window(params, full, mask, origin, size):
     og = OS.to_storage(wp, out["pops"]).numpy()[(slice(None),) + kk]
     gg = p1[(slice(None),) + sel][(slice(None),) + kk]
     dpop = np.abs(og - gg)[:, fl]
-    res = {"pop_abs": float(dpop.max()),
-           "pop_beyond_half_fp16_ulp": float((dpop - 2.0 ** -11 * np.abs(og[:, fl]) - 2.0 ** -25).max()),
-           "cells": int(fl.sum())}
+    beyond = dpop - 2.0 ** -11 * np.abs(og[:, fl]) - 2.0 ** -25
+    w = np.unravel_index(int(np.argmax(beyond)), beyond.shape)
+    res = {"pop_abs": float(dpop.max()), "pop_beyond_half_fp16_ulp": float(beyond.max()),
+           "cells": int(fl.sum()),
+           "worst": {"i": int(w[0]), "oracle": float(og[:, fl][w]), "gpu": float(gg[:, fl][w])}}
     if s1.shape[0]:
         os_ = out["scal"].numpy()[(slice(None),) + kk]
         gs = s1[(slice(None),) + sel][(slice(None),) + kk]
         scale = np.maximum(np.array(params["weno_scale"][:s1.shape[0]]).reshape(-1, 1), np.abs(os_[:, fl]))
         res["scal_rel"] = float((np.abs(gs - os_)[:, fl] / scale).max())
     return res
+
+
+def _developed(params, P, u, scal, seed, amp=2e-3):
+    """A developed, non-equilibrium stored state built on the host from the workload's
+    fields: the oracle's equilibrium (Eq. 6) plus a seeded random deviation, populations
+    rounded to the storage precision, scalars to theirs."""
+    st = OS.init_state(params, torch.from_numpy(P), torch.from_numpy(u),
+                       None if scal is None else torch.from_numpy(scal))
+    gh = OS.to_storage(params, st["pops"]).numpy()
+    del st
+    Q = gh.shape[0]
+    for i in range(Q):        # one population at a time keeps the host memory bounded
+        gh[i] += L.random_deviation(1, gh.shape[1:], seed + i, amp)[0]
+    gh = gh.astype(STORE_NP[params["precision"]])
+    sc = None if scal is None else scal.astype(SCAL_NP[params["precision"]])
+    return gh, sc
+
+
+def _gpu_run_from(params, state, steps):
+    from paper_2207_11567_amd import Solver
+    gh, sc = state
+    s = Solver(params)
+    s.set_state(torch.from_numpy(gh), None if sc is None else torch.from_numpy(sc), 0)
+    s.step(steps)
+    p1, s1, k = s.get_state()
+    assert k == steps
+    out = [t.double().cpu().numpy() for t in (p1, s1)]
+    s.close()
+    return out + [None, None, None, steps]
 
 
 def _check(res, prec, steps):
@@ -243,3 +282,37 @@ def test_large_grid_instances_match_a_tiled_small_grid(phys, prec, n, reps):
     assert k0 == k1 == steps
     assert np.array_equal(np.tile(p0, (1,) + reps), p1)
     assert np.array_equal(np.tile(s0, (1,) + reps), s1)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
+def test_hit_256_developed_state_windows(prec):
+    """One step of the full 256^3 HIT grid (cached-pull instance) from a developed state
+    (equilibrium of the workload's field plus a seeded non-equilibrium part), against the
+    oracle on windows of that same stored state."""
+    params, P, u = L.hit(256)
+    params["precision"] = prec
+    state = _developed(params, P, u, None, 9100)
+    print(f"developed HIT 256^3 {prec}: state built", flush=True)
+    full = _gpu_run_from(params, state, 1)
+    for origin in ((0, 0, 0), (120, 37, 250), (249, 128, 64)):
+        res = _window(params, full, None, origin, (10, 10, 10), state=state)
+        print(prec, origin, res, flush=True)
+        if prec == "fp16s":
+            assert res["pop_beyond_half_fp16_ulp"] <= 2e-7, res
+        else:
+            _check(res, prec, 1)
+
+
+def test_reacting_box_fp16_storage_developed_state_windows():
+    """The reacting box in FP16 storage (split step) from a developed stored state."""
+    params, P, u, scal = L.reacting_box()
+    params["precision"] = "fp16s"
+    state = _developed(params, P, u, scal, 9200)
+    print("developed reacting box fp16s: state built", flush=True)
+    full = _gpu_run_from(params, state, 1)
+    for origin, size in (((50, 60, 0), (12, 12, 10)), ((90, 100, 184), (12, 12, 16)),
+                         ((180, 3, 374), (12, 12, 10))):
+        res = _window(params, full, None, origin, size, state=state)
+        print("reacting fp16s", origin, res, flush=True)
+        assert res["pop_beyond_half_fp16_ulp"] <= 2e-7, res
+        assert res["scal_rel"] <= 2e-6, res
