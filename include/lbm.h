@@ -236,6 +236,20 @@ lbm_status lbm_probe_rows(lbm_solver *s, int64_t *rows);
  * Needs a temperature (S >= 1).  Synchronises. */
 lbm_status lbm_flame_surface(lbm_solver *s, double T_u, double T_b, double *surface_host);
 
+/* The flame surface of lbm_flame_surface, for callers that cannot allocate or synchronise
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * allocates nothing and does not synchronise.  Its partial sums live in a device scratch
+ * array of the library (about 9.5 MB per device, held until the process ends), not in the
+ * solver's work buffer; grids up to 131072 blocks of 256 cells (33,554,432 cells) are
+ * accepted, larger ones return LBM_E_INVALID.  The sum (FP64, bit for bit the value
+ * lbm_flame_surface returns) is written to surface_dev, a device double, in stream order.
+ * All calls on one device share that device's scratch: calls that overlap in time on one
+ * device (different streams, threads or solvers) race and must be ordered by the caller.
+ * Errors: LBM_E_INVALID (NULL pointers, no temperature, T_b == T_u, too many cells),
+ * LBM_E_STATE (before initialisation), LBM_E_HIP (launch failure, or the scratch address
+ * could not be resolved on the solver's device). */
+lbm_status lbm_flame_surface_noalloc(lbm_solver *s, double T_u, double T_b, double *surface_dev);
+
 /* Thermodynamic pressure state of the current level, three FP64 values on the host:
  * pi = P_th/P_th(0), q = dln(pi)/dt of this level (per time step), K = the held
  * mass constant (0 until the first step of a closed domain fixes it).  Open domains keep

@@ -100,6 +100,7 @@ def _load():
         "lbm_set_probes": [c_void_p, P(ctypes.c_int64), c_int32, c_void_p, ctypes.c_int64],
         "lbm_probe_rows": [c_void_p, P(ctypes.c_int64)],
         "lbm_flame_surface": [c_void_p, c_double, c_double, P(c_double)],
+        "lbm_flame_surface_noalloc": [c_void_p, c_double, c_double, c_void_p],
         "lbm_set_thermo_pressure": [c_void_p, P(c_double)],
     }
     for name, args in sig.items():

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -56,6 +57,8 @@ struct lbm_solver {
   int probe[8];
   long long probe_cap, probe_rows;
   void *geom;
+  double *scratch;     // this device's copy of the allocation-free scratch (or nullptr)
+  std::string scratch_err;
   std::string err;
 };
 
@@ -370,6 +373,52 @@ static hipError_t launch_step_pass(lbm_solver *s, const StepArgs &a0) {
   return e;
 }
 
+// ------------------------------------------------------------------ allocation-free surface
+// Device scratch of lbm_flame_surface_noalloc, held by the library on every device it runs
+// on until the process ends: the surface kernel's block records [NOALLOC_MAX_BLOCKS][NSUM],
+// then the 256 stage records of the two-stage sum, then the NSUM final sums.  Every record
+// a call reads was written earlier in the same call, so nothing needs clearing.  In host
+// code the name `scratch` only stands in for the symbol: its device address comes from
+// hipGetSymbolAddress, once per device, and is kept in g_scratch_ptr.
+constexpr int NOALLOC_MAX_BLOCKS = 131072;                        // 33.5 M cells, 256 per block
+constexpr size_t NOALLOC_STAGE = (size_t)NOALLOC_MAX_BLOCKS * NSUM;
+constexpr size_t NOALLOC_OUT = NOALLOC_STAGE + (size_t)256 * NSUM;
+static __device__ __align__(256) double scratch[NOALLOC_OUT + NSUM];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static bool g_scratch_looked_up[NOALLOC_MAX_DEVICES];
+static double *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static hipError_t g_scratch_status[NOALLOC_MAX_DEVICES];
+
+// The scratch address on the current device (looked up once per device); nullptr with the
+// reason in why when the lookup failed.
+static double *scratch_on_current_device(std::string &why) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    why = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    why = "device index beyond the scratch table";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_looked_up[dev]) {
+    void *ptr = nullptr;
+    g_scratch_status[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_status[dev] == hipSuccess ? (double *)ptr : nullptr;
+    g_scratch_looked_up[dev] = true;
+  }
+  if (!g_scratch_ptr[dev]) why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(g_scratch_status[dev]);
+  return g_scratch_ptr[dev];
+}
+
+static __global__ void copy_first_kernel(const double *src, double *dst) {
+  if (threadIdx.x == 0) dst[0] = src[0];
+}
+
 extern "C" {
 
 lbm_status lbm_query_sizes(const lbm_params *p, size_t *pop_bytes, size_t *scal_bytes, size_t *work_bytes) {
@@ -434,6 +483,7 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
   s->nprobe = 0;
   s->probe_cap = s->probe_rows = 0;
   s->geom = s->work + L.off_geom;
+  s->scratch = scratch_on_current_device(s->scratch_err);   // the solver's device is the current one
   hipError_t e = hipMemsetAsync(s->work, 0, 256, s->stream);
   if (e == hipSuccess) e = launch_set_thermo(s->thermo, 1.0, 0.0, 0.0, s->stream);
   if (e == hipSuccess) e = build_cell_list(s);
@@ -711,6 +761,42 @@ lbm_status lbm_flame_surface(lbm_solver *s, double T_u, double T_b, double *surf
   if (e == hipSuccess) e = hipMemcpyAsync(surface_host, s->sums, sizeof(double), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "flame surface");
+  return LBM_OK;
+}
+
+lbm_status lbm_flame_surface_noalloc(lbm_solver *s, double T_u, double T_b, double *surface_dev) {
+  if (!s || !surface_dev) return LBM_E_INVALID;
+  if (s->nblocks > NOALLOC_MAX_BLOCKS) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "flame surface (no allocation): %lld cells exceed the scratch maximum of %lld",
+             s->N, (long long)NOALLOC_MAX_BLOCKS * 256);
+    s->err = buf;
+    return LBM_E_INVALID;
+  }
+  if (s->NS < 1 || !(T_b != T_u)) {
+    s->err = "flame surface: needs a temperature and T_b != T_u";
+    return LBM_E_INVALID;
+  }
+  if (!s->initialized) {
+    s->err = "flame surface before initialisation";
+    return LBM_E_STATE;
+  }
+  if (!s->scratch) {
+    s->err = "flame surface (no allocation): " + s->scratch_err;
+    return LBM_E_HIP;
+  }
+  StepArgs a = make_args(s);
+  a.scal_in = s->scal[s->cur];
+  a.partials = s->scratch;
+  hipError_t e = launch_surface(s->Q, s->prec, a, s->nblocks, s->stream, T_u, T_b);
+  if (e == hipSuccess)
+    e = launch_finalize(s->scratch, s->nblocks, s->scratch + NOALLOC_STAGE, s->scratch + NOALLOC_OUT, s->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(copy_first_kernel, dim3(1), dim3(64), 0, s->stream, (const double *)(s->scratch + NOALLOC_OUT),
+                       surface_dev);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return hip_fail(s, e, "flame surface (no allocation)");
   return LBM_OK;
 }
 

@@ -164,6 +164,14 @@ class Solver:
         self._chk(C.lib().lbm_flame_surface(self._h, float(T_u), float(T_b), ctypes.byref(v)))
         return v.value
 
+    def flame_surface_noalloc(self, T_u, T_b, out):
+        """The flame surface written to `out` (a float64 device tensor of one element) in
+        stream order, without allocation or synchronisation."""
+        if out.dtype != torch.float64 or out.device != self.device or out.numel() < 1:
+            raise ValueError("out must be a float64 tensor on the solver's device")
+        self._chk(C.lib().lbm_flame_surface_noalloc(self._h, float(T_u), float(T_b), _ptr(out)))
+        return out
+
     def get_state(self):
         pops = torch.empty((self.Q,) + self.shape, dtype=self.pop_dtype, device=self.device)
         scal = torch.empty((self.NS,) + self.shape, dtype=self.scal_dtype, device=self.device)
