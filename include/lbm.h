@@ -116,7 +116,26 @@ typedef struct {
   int32_t galilean;        /* 0 | 1: Galilean correction of the cumulant collision (Geier
                               et al. 2015, whose operator Sec. 2.2 applies), see below;
                               requires LBM_CUMULANT */
+  int32_t fourth_order;    /* 0 | 1: D3Q27 only, requires LBM_CUMULANT: the higher-order
+                              cumulant relaxation of Geier, Pasquali and Schoenherr (2017)
+                              for fourth-order accurate diffusion, see below (omega_high is
+                              then unused) */
 } lbm_params;
+
+/* Fourth-order parameterisation (Geier, Pasquali, Schoenherr 2017, J. Comput. Phys. 348,
+ * "Parametrization of the cumulant lattice Boltzmann method for fourth order accurate
+ * diffusion, part I"; the paper's operator, Sec. 2.2, has one rate per cumulant, W = diag(
+ * omega_0 .. omega_xxyyzz)): with omega_1 the shear rate of the cell and omega_2 = omega_bulk,
+ * the third-order sums C_120 + C_102, C_210 + C_012, C_201 + C_021 relax to zero at
+ * omega_3(omega_1, omega_2), their differences at omega_4, C_111 at omega_5; the fourth-order
+ * cumulants are set to C_220 = -(2/3) A (1/omega_1 - 1/2)(d_x u_x + d_y u_y) and
+ * C_112 = -(1/3) B (1/omega_1 - 1/2)(d_x u_y + d_y u_x) (and permutations), the velocity
+ * gradients estimated from the pre-collision second cumulants; fifth and sixth order relax to
+ * zero.  The rates are rational functions of omega_1 and omega_2 that leave (0, 2) around
+ * omega_1 = 1.55 (for omega_2 = 1) and A, B are singular at omega_1 = omega_2: lbm_create
+ * rejects molecular shear rates for which omega_3..5 leave (0, 2) or A, B are not finite;
+ * the sub-grid model lowers the cell's rate below the molecular one, and no limiter is
+ * applied.  Not covered by the adjoint. */
 
 /* Galilean correction: on D2Q9 and D3Q27 c^3 = c, so the equilibrium third diagonal moment
  * lacks u_a^3 and the viscous stress picks up (1/omega - 1/2) 3 u_a^2 d_a u_a on each

@@ -22,7 +22,7 @@ def base_params(lattice, nx, ny, nz=1, **kw):
              T_ref=300.0, face_bc=list(FACES), inlet_u=[0.0, 0.0, 0.0], inlet_noise=0.0,
              outlet_P=1.0 * CS2, inlet_T=300.0, inlet_Y=[0.0] * 8, weno_scale=[1.0] * 8,
              chem=[0.0] * 32, seed=2207, pth_mode="open", gamma=1.4,
-             transport_model="simple", transport=[0.0] * 32, galilean=0)
+             transport_model="simple", transport=[0.0] * 32, galilean=0, fourth_order=0)
     p.update(kw)
     return p
 

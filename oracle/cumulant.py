@@ -193,6 +193,65 @@ def relax(lat, C, omega_s, omega_bulk, omega_high, u=None):
     return Cs
 
 
+def parameterised_rates(omega_1, omega_2):
+    """Rates of the third-order cumulants and coefficients of the fourth-order equilibria
+    of the parameterisation of Geier, Pasquali and Schoenherr (2017, J. Comput. Phys. 348,
+    "Parametrization of the cumulant lattice Boltzmann method for fourth order accurate
+    diffusion, part I"), functions of the shear rate omega_1 and the bulk rate omega_2:
+    omega_3 for the sums C_120 + C_102 (and their permutations), omega_4 for the
+    differences, omega_5 for C_111, A and B for the equilibria of the fourth-order
+    diagonal and mixed cumulants.  Singular where omega_1 = omega_2."""
+    w1, w2 = omega_1, omega_2
+    w3 = (8 * (w1 - 2) * (w2 * (3 * w1 - 1) - 5 * w1)) / (8 * (5 - 2 * w1) * w1 + w2 * (8 + w1 * (9 * w1 - 26)))
+    w4 = (8 * (w1 - 2) * (w1 + w2 * (3 * w1 - 7))) / (w2 * (56 - 42 * w1 + 9 * w1 * w1) - 8 * w1)
+    w5 = (24 * (w1 - 2) * (4 * w1 * w1 + w1 * w2 * (18 - 13 * w1) + w2 * w2 * (2 + w1 * (6 * w1 - 11)))) / (
+        16 * w1 * w1 * (w1 - 6) - 2 * w1 * w2 * (216 + 5 * w1 * (9 * w1 - 46))
+        + w2 * w2 * (w1 * (3 * w1 - 10) * (15 * w1 - 28) - 48))
+    den = (w1 - w2) * (w2 * (2 + 3 * w1) - 8 * w1)
+    A = (4 * w1 * w1 + 2 * w1 * w2 * (w1 - 6) + w2 * w2 * (w1 * (10 - 3 * w1) - 4)) / den
+    B = (4 * w1 * w2 * (9 * w1 - 16) - 4 * w1 * w1 - 2 * w2 * w2 * (2 + 9 * w1 * (w1 - 2))) / (3 * den)
+    return w3, w4, w5, A, B
+
+
+def relax_parameterised(lat, C, omega_s, omega_bulk, u=None):
+    """The relaxation of Geier et al. (2017) for D3Q27 (fourth-order accurate diffusion):
+    second order as in relax() (with the Galilean correction when u is given); the
+    third-order sums C_120 + C_102, C_210 + C_012, C_201 + C_021 relax to zero at
+    omega_3, their differences at omega_4, C_111 at omega_5; the fourth-order cumulants
+    are set to equilibria proportional to the velocity gradients (rate one),
+    C_220 = -(2/3) A (1/omega_s - 1/2)(d_x u_x + d_y u_y) (and permutations),
+    C_112 = -(1/3) B (1/omega_s - 1/2)(d_x u_y + d_y u_x) (and permutations), the
+    gradients estimated from the pre-collision second cumulants (diagonal as in
+    diagonal_strain, mixed d_a u_b + d_b u_a = -(omega_s/cs2) C_ab); fifth and sixth
+    order relax to zero."""
+    assert lat.D == 3, "the fourth-order parameterisation is defined for D3Q27"
+    Cs = relax(lat, {e: v for e, v in C.items() if sum(e) == 2}, omega_s, omega_bulk, 1.0, u)
+    w3, w4, w5, A, B = parameterised_rates(omega_s, omega_bulk)
+    # third order: (x y y, x z z) pairs and the like, by the axis that appears once
+    for a in range(3):
+        b, c = [d for d in range(3) if d != a]
+        e_b = _unit(3, a, b, b)          # e.g. C_120 for a = x: x y y
+        e_c = _unit(3, a, c, c)          #      C_102:          x z z
+        S = C[e_b] + C[e_c]
+        Dif = C[e_b] - C[e_c]
+        Cs[e_b] = 0.5 * ((1.0 - w3) * S + (1.0 - w4) * Dif)
+        Cs[e_c] = 0.5 * ((1.0 - w3) * S - (1.0 - w4) * Dif)
+    Cs[(1, 1, 1)] = (1.0 - w5) * C[(1, 1, 1)]
+    # fourth order
+    dd = diagonal_strain(lat, C, omega_s, omega_bulk)
+    visc = 1.0 / omega_s - 0.5
+    for a in range(3):
+        for b in range(a + 1, 3):
+            Cs[_unit(3, a, a, b, b)] = -(2.0 / 3.0) * A * visc * (dd[a] + dd[b])
+            c = 3 - a - b
+            mixed = -omega_s / CS2 * C[_unit(3, a, b)]          # d_a u_b + d_b u_a
+            Cs[_unit(3, a, b, c, c)] = -(1.0 / 3.0) * B * visc * mixed
+    for e, v in C.items():
+        if sum(e) >= 5:
+            Cs[e] = torch.zeros_like(v)
+    return Cs
+
+
 def central_to_raw(lat, kappa, u):
     """m_e = sum_{k <= e} prod_d binom(e_d, k_d) u_d^{e_d - k_d} kappa_k
     (expansion of c = (c - u) + u in the moment definition)."""
@@ -209,12 +268,15 @@ def central_to_raw(lat, kappa, u):
     return m
 
 
-def cumulant_collide(lat, f_prime, u, nu, cs_smag, omega_bulk, omega_high, omega_s=None, galilean=False):
+def cumulant_collide(lat, f_prime, u, nu, cs_smag, omega_bulk, omega_high, omega_s=None, galilean=False,
+                     fourth_order=False):
     """Post-collision pre-conditioned populations f'* (Eq. 9 as read).
 
     f_prime: (Q, *grid); u: (D, *grid) the velocity of Eq. 7b; nu: molecular kinematic
     viscosity (scalar or *grid); omega_s, if given, replaces the shear rate of Eq. 12 and
-    the sub-grid model; galilean adds the Galilean correction.  Returns (f'*, omega_s)."""
+    the sub-grid model; galilean adds the Galilean correction; fourth_order selects the
+    parameterised relaxation of Geier et al. (2017) (D3Q27; omega_high is then unused).
+    Returns (f'*, omega_s)."""
     nd = f_prime.ndim - 1
     w = lat.w.reshape((-1,) + (1,) * nd)
     m0 = f_prime.sum(0)
@@ -223,7 +285,10 @@ def cumulant_collide(lat, f_prime, u, nu, cs_smag, omega_bulk, omega_high, omega
     if omega_s is None:
         omega_s = smagorinsky_omega(lat, kappa, nu, cs_smag)
     C = moments_to_cumulants(kappa)
-    Cs = relax(lat, C, omega_s, omega_bulk, omega_high, u if galilean else None)
+    if fourth_order:
+        Cs = relax_parameterised(lat, C, omega_s, omega_bulk, u if galilean else None)
+    else:
+        Cs = relax(lat, C, omega_s, omega_bulk, omega_high, u if galilean else None)
     kappa_s = cumulants_to_moments(Cs, m0)
     for e in lat.exps:           # orders 0 and 1 pass through unrelaxed
         if sum(e) < 2:

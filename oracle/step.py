@@ -181,7 +181,8 @@ def step(params, state):
     if params["collision"] == "cumulant":
         fps, _ = cumulant.cumulant_collide(lat, fp, u, nu, params["cs_smag"],
                                            params["omega_bulk"], params["omega_high"],
-                                           galilean=bool(params.get("galilean", 0)))
+                                           galilean=bool(params.get("galilean", 0)),
+                                           fourth_order=bool(params.get("fourth_order", 0)))
     else:
         w = lat.w.reshape((-1,) + (1,) * 3)
         f_t = fp - w * (fp.sum(0) - 1.0)

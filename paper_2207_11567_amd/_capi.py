@@ -35,7 +35,7 @@ class LbmParams(ctypes.Structure):
                 ("weno_scale", c_double * 8), ("chem", c_double * 32), ("seed", c_uint64),
                 ("pth_mode", c_int32), ("gamma", c_double),
                 ("transport_model", c_int32), ("transport", c_double * 32),
-                ("galilean", c_int32)]
+                ("galilean", c_int32), ("fourth_order", c_int32)]
 
 
 def make_params(d):
@@ -67,6 +67,7 @@ def make_params(d):
     for i, v in enumerate(list(d.get("transport", [0.0] * 32))[:32]):
         p.transport[i] = float(v)
     p.galilean = int(d.get("galilean", 0))
+    p.fourth_order = int(d.get("fourth_order", 0))
     return p
 
 

@@ -95,6 +95,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(KArgs<typename Prec<PREC>:
   rt.wb = a.wb;
   rt.wh = a.wh;
   rt.gal = false;
+  rt.p4 = false;
   collide_d3q27_vjp(g, mom, rt, lam, lu);
   // transposed streaming: the adjoint of g_i(r) = A_i(r - c_i) is pushed to r - c_i
 #pragma unroll

@@ -96,6 +96,28 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   if (p->collision != LBM_CUMULANT && p->collision != LBM_BGK) return fail("unknown collision operator");
   if (p->galilean != 0 && p->galilean != 1) return fail("galilean must be 0 or 1");
   if (p->galilean && p->collision != LBM_CUMULANT) return fail("the Galilean correction belongs to the cumulant collision");
+  if (p->fourth_order != 0 && p->fourth_order != 1) return fail("fourth_order must be 0 or 1");
+  if (p->fourth_order) {
+    if (p->lattice != LBM_D3Q27 || p->collision != LBM_CUMULANT)
+      return fail("the fourth-order parameterisation belongs to the D3Q27 cumulant collision");
+    // rates at the molecular shear rate (Eq. 12 read as a relaxation time)
+    const double w1 = 1.0 / (3.0 * p->nu_ref + 0.5), w2 = p->omega_bulk;
+    const double w3 = (8 * (w1 - 2) * (w2 * (3 * w1 - 1) - 5 * w1)) / (8 * (5 - 2 * w1) * w1 + w2 * (8 + w1 * (9 * w1 - 26)));
+    const double w4 = (8 * (w1 - 2) * (w1 + w2 * (3 * w1 - 7))) / (w2 * (56 - 42 * w1 + 9 * w1 * w1) - 8 * w1);
+    const double w5 = (24 * (w1 - 2) * (4 * w1 * w1 + w1 * w2 * (18 - 13 * w1) + w2 * w2 * (2 + w1 * (6 * w1 - 11)))) /
+                      (16 * w1 * w1 * (w1 - 6) - 2 * w1 * w2 * (216 + 5 * w1 * (9 * w1 - 46)) +
+                       w2 * w2 * (w1 * (3 * w1 - 10) * (15 * w1 - 28) - 48));
+    const double den = (w1 - w2) * (w2 * (2 + 3 * w1) - 8 * w1);
+    const bool ok = w3 > 0 && w3 < 2 && w4 > 0 && w4 < 2 && w5 > 0 && w5 < 2 && fabs(den) > 1e-3;
+    if (!ok) {
+      char b2[200];
+      snprintf(b2, sizeof b2,
+               "fourth-order parameterisation outside its stable range at omega_1 = %g, omega_bulk = %g "
+               "(omega_3..5 = %g, %g, %g)", w1, w2, w3, w4, w5);
+      err = b2;
+      return LBM_E_INVALID;
+    }
+  }
   const int NS = n_scalars(p->physics);
   if (NS < 0) return fail("unknown physics");
   if (p->visc_law != LBM_VISC_CONST_NU && p->visc_law != LBM_VISC_CONST_MU) return fail("unknown visc_law");
@@ -233,6 +255,7 @@ static StepArgs make_args(const lbm_solver *s) {
   a.step = s->step;
   a.collision = p.collision;
   a.gal = p.galilean;
+  a.p4 = p.fourth_order;
   a.remap = 1;
   // population copies larger than the 256 MB Infinity Cache: cached pull loads
   a.pull_cached = (size_t)s->Q * (size_t)s->N * pop_elem(s->prec) > ((size_t)256 << 20);
@@ -835,6 +858,7 @@ static lbm_status adjoint_supported(lbm_solver *s) {
   else if (p.collision != LBM_CUMULANT) why = "the adjoint covers the cumulant collision";
   else if (p.omega_high != 1.0) why = "the adjoint needs omega_high == 1";
   else if (p.galilean) why = "the adjoint covers the collision without the Galilean correction";
+  else if (p.fourth_order) why = "the adjoint covers the collision without the fourth-order parameterisation";
   else if (p.precision == LBM_FP16S) why = "the adjoint runs in FP64 or FP32";
   else if (s->has_geom) why = "the adjoint covers domains without solid cells";
   else if (s->closed) why = "the adjoint covers a constant thermodynamic pressure";

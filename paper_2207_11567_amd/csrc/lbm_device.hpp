@@ -100,6 +100,7 @@ template <class R> struct Rates {
   R smag18;    // 18 Cs^2 = 2 Cs^2 / cs2^2
   R wb, wh;    // bulk and higher-order rates
   bool gal;    // Galilean correction of the diagonal second-order cumulants
+  bool p4;     // D3Q27: parameterised higher-order relaxation (fourth-order diffusion)
 };
 
 template <class R>
@@ -233,11 +234,54 @@ __device__ __forceinline__ R collide_d3q27(R (&d)[27], R ux, R uy, R uz, const R
   const R As = (Tr + Dxy + Dxz) * R(1.0 / 3.0);
   const R Bs = As - Dxy, Cs = As - Dxz;
   const R q110 = o1 * k110, q101 = o1 * k101, q011 = o1 * k011;
-  const R q210 = h * k210, q201 = h * k201, q120 = h * k120, q021 = h * k021, q102 = h * k102,
-          q012 = h * k012, q111 = h * k111;
-  const R q211 = h * c211, q121 = h * c121, q112 = h * c112, q220 = h * c220, q202 = h * c202,
-          q022 = h * c022;
-  const R q221 = h * c221, q212 = h * c212, q122 = h * c122, q222 = h * c222;
+  R q210 = h * k210, q201 = h * k201, q120 = h * k120, q021 = h * k021, q102 = h * k102,
+    q012 = h * k012, q111 = h * k111;
+  R q211 = h * c211, q121 = h * c121, q112 = h * c112, q220 = h * c220, q202 = h * c202,
+    q022 = h * c022;
+  R q221 = h * c221, q212 = h * c212, q122 = h * c122, q222 = h * c222;
+  if constexpr (!HIGH1) {
+    if (rt.p4) {
+      // Parameterisation of Geier, Pasquali and Schoenherr (2017) for fourth-order accurate
+      // diffusion: third-order rates from the shear rate om and the bulk rate wb (sums
+      // C_120 + C_102 and permutations at w3, their differences at w4, C_111 at w5), the
+      // fourth-order cumulants set to equilibria proportional to the velocity gradients
+      // estimated from the pre-collision second cumulants, fifth and sixth order to zero.
+      const R w1 = om, w2 = rt.wb;
+      const R w3 = fdiv(R(8) * (w1 - R(2)) * (w2 * (R(3) * w1 - R(1)) - R(5) * w1),
+                        R(8) * (R(5) - R(2) * w1) * w1 + w2 * (R(8) + w1 * (R(9) * w1 - R(26))));
+      const R w4 = fdiv(R(8) * (w1 - R(2)) * (w1 + w2 * (R(3) * w1 - R(7))),
+                        w2 * (R(56) - R(42) * w1 + R(9) * w1 * w1) - R(8) * w1);
+      const R w5 = fdiv(R(24) * (w1 - R(2)) *
+                            (R(4) * w1 * w1 + w1 * w2 * (R(18) - R(13) * w1) + w2 * w2 * (R(2) + w1 * (R(6) * w1 - R(11)))),
+                        R(16) * w1 * w1 * (w1 - R(6)) - R(2) * w1 * w2 * (R(216) + R(5) * w1 * (R(9) * w1 - R(46))) +
+                            w2 * w2 * (w1 * (R(3) * w1 - R(10)) * (R(15) * w1 - R(28)) - R(48)));
+      const R iden = fdiv(R(1), (w1 - w2) * (w2 * (R(2) + R(3) * w1) - R(8) * w1));
+      const R cA = (R(4) * w1 * w1 + R(2) * w1 * w2 * (w1 - R(6)) + w2 * w2 * (w1 * (R(10) - R(3) * w1) - R(4))) * iden;
+      const R cB = (R(4) * w1 * w2 * (R(9) * w1 - R(16)) - R(4) * w1 * w1 -
+                    R(2) * w2 * w2 * (R(2) + R(9) * w1 * (w1 - R(2)))) * iden * R(1.0 / 3.0);
+      const R h3 = R(0.5) * (R(1) - w3), h4 = R(0.5) * (R(1) - w4);
+      q120 = h3 * (k120 + k102) + h4 * (k120 - k102);
+      q102 = h3 * (k120 + k102) - h4 * (k120 - k102);
+      q210 = h3 * (k210 + k012) + h4 * (k210 - k012);
+      q012 = h3 * (k210 + k012) - h4 * (k210 - k012);
+      q201 = h3 * (k201 + k021) + h4 * (k201 - k021);
+      q021 = h3 * (k201 + k021) - h4 * (k201 - k021);
+      q111 = (R(1) - w5) * k111;
+      // d_a u_a = -(om / 2) (3 A_a - tr) - (wb / 2) tr (tr of the cs2-shifted diagonal);
+      // d_a u_b + d_b u_a = -3 om k_ab
+      const R tr = A + B + C, ho = R(0.5) * om, tb = R(0.5) * w2 * tr;
+      const R dx = -ho * (R(3) * A - tr) - tb, dy = -ho * (R(3) * B - tr) - tb, dz = -ho * (R(3) * C - tr) - tb;
+      const R vis = fdiv(R(1), om) - R(0.5);
+      const R fa = R(-2.0 / 3.0) * cA * vis, fb = cB * vis * om;   // -(1/3) B vis (-3 om k)
+      q220 = fa * (dx + dy);
+      q202 = fa * (dx + dz);
+      q022 = fa * (dy + dz);
+      q112 = fb * k110;
+      q121 = fb * k101;
+      q211 = fb * k011;
+      q221 = q212 = q122 = q222 = R(0);
+    }
+  }
 
   // back to deviation central moments: kappa*^d = kappa* - kappa^w
   KD(2, 0, 0) = As - ux2;

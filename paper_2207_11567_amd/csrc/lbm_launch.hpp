@@ -37,12 +37,13 @@ hipError_t launch_statistics(const double *acc, int D, long long N, long long k,
                              hipStream_t st);
 
 // Collision instance for the parameters: BGK, or the cumulant operator with every order
-// >= 3 at rate one (decided in the compute precision, as the kernel would), or general.
+// >= 3 at rate one (decided in the compute precision, as the kernel would), or general
+// (other rates, or the parameterised higher orders, a runtime switch of that instance).
 template <int Q, int PREC>
 int collision_instance(const StepArgs &a) {
   using R = typename Prec<PREC>::R;
   if (a.collision != 0) return COLL_BGK;
-  return (Q == 27 && (R)a.wh != R(1)) ? COLL_CUM : COLL_CUM1;
+  return (Q == 27 && ((R)a.wh != R(1) || a.p4)) ? COLL_CUM : COLL_CUM1;
 }
 
 template <int Q, int PREC, int NS, bool FULL, int MODE>

@@ -70,6 +70,7 @@ struct StepArgs {
   long long step;
   int collision;       // 0 cumulant, 1 BGK
   int gal;             // Galilean correction of the cumulant collision
+  int p4;              // D3Q27 parameterised higher-order relaxation (fourth-order diffusion)
   int remap;           // XCD-aware block order
   int band_rows;       // 0: linear 256-cell tiles; else 64x4 tiles in bands of this many rows
   int pull_cached;     // production instance with cached pull loads (else streaming loads)
@@ -105,7 +106,7 @@ template <class R> struct KArgs {
   int nx, ny, nz, N;
   int face[6];
   long long step;
-  int collision, remap, band_rows, gal;
+  int collision, remap, band_rows, gal, p4;
   R P0, invP0, wb, wh, smag18, kap;
   R inlet_u[3], outlet_P;
   double inlet_noise;
@@ -130,6 +131,7 @@ template <class R> KArgs<R> to_kargs(const StepArgs &a) {
   for (int f = 0; f < 6; ++f) k.face[f] = a.face[f];
   k.step = a.step; k.collision = a.collision; k.remap = a.remap; k.band_rows = a.band_rows;
   k.gal = a.gal;
+  k.p4 = a.p4;
   k.P0 = (R)a.P0; k.invP0 = (R)(1.0 / a.P0); k.wb = (R)a.wb; k.wh = (R)a.wh; k.smag18 = (R)a.smag18;
   for (int d = 0; d < 3; ++d) k.inlet_u[d] = (R)a.inlet_u[d];
   k.outlet_P = (R)a.outlet_P; k.inlet_noise = a.inlet_noise;
@@ -951,6 +953,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         rt.wb = a.wb;
         rt.wh = a.wh;
         rt.gal = a.gal != 0;
+        rt.p4 = a.p4 != 0;
         const R hP0 = R(0.5) * a.invP0;
         const R base = sg + Xs * hP0;                    // (1/r) m0 - 1
         const R invr = rho0 * a.invP0 * s;              // rho/rho_ref = rho cs2/P0

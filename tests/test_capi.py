@@ -42,6 +42,9 @@ def test_exports_every_declared_symbol():
     ({"lattice": "D3Q27", "nx": 1024, "ny": 1024, "nz": 100}, "too large"),
     ({"nx": 0}, ">= 1"),
     ({"galilean": 1, "collision": "bgk"}, "cumulant"),
+    ({"fourth_order": 1}, "D3Q27"),
+    ({"fourth_order": 1, "lattice": "D3Q27", "nz": 4, "nu_ref": 1.0 / 18.0}, "stable range"),
+    ({"fourth_order": 1, "lattice": "D3Q27", "nz": 4, "nu_ref": 1.0 / 6.0, "omega_bulk": 1.0}, "stable range"),
 ])
 def test_validation_rejects(change, needle):
     C, lib = _lib()

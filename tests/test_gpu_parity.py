@@ -45,7 +45,7 @@ def _params(lat, shape, phys, coll, faces=None, **kw):
     return p
 
 
-def _compare(params, ghat, scal, steps, solid=None, tol_pop=1e-12, tol_scal=1e-12, faces_note=""):
+def _compare(params, ghat, scal, steps, solid=None, tol_pop=1e-12, tol_scal=1e-12, faces_note="", tol_sums=1e-12):
     s = make_solver(params)
     if solid is not None:
         s.set_geometry(torch.from_numpy(solid.astype(np.uint8)))
@@ -68,7 +68,7 @@ def _compare(params, ghat, scal, steps, solid=None, tol_pop=1e-12, tol_scal=1e-1
         assert rel <= tol_scal, f"scalars differ by {rel} of their range {faces_note}"
     o_sums = sums.numpy()
     dsum = np.abs(np.array(g_sums) - o_sums) / np.maximum(np.abs(o_sums), 1.0)
-    assert dsum.max() <= 1e-12, (g_sums, o_sums)
+    assert dsum.max() <= tol_sums, (g_sums, o_sums)
     s.close()
 
 
