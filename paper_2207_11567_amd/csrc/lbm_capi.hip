@@ -145,6 +145,58 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
       if (!(p->chem[k] > 0.0)) return fail("two-step chemistry needs molar masses > 0");
     if (!(p->chem[4] > 0.0) || !(p->chem[17] > 0.0)) return fail("two-step chemistry needs c_p > 0, W_ref > 0");
   }
+  // The same explicit-diffusion limit in the hottest gas the chemistry can make, where the
+  // density is lowest: with rho nu constant the kinematic viscosity (and F D = F nu/Pr)
+  // grows as rho_ref/rho; with mixture transport the binary coefficients grow as
+  // (T/T_ref)^s_D and lambda/(rho c_p) as (T/T_ref)^s_mu rho_ref/rho.  Hottest gas: T_ad of
+  // the one-step model, or the inlet mixture burnt completely to CO2 and H2O (two-step).
+  if ((p->physics == LBM_ONE_STEP || p->physics == LBM_TWO_STEP) &&
+      (p->visc_law == LBM_VISC_CONST_MU || p->transport_model == LBM_TRANSPORT_MIXTURE)) {
+    const double Dm = p->lattice == LBM_D2Q9 ? 2.0 : 3.0;
+    double T_hot = 0.0, rho_ratio = 1.0;        // rho_ref / rho at T_hot
+    if (p->physics == LBM_ONE_STEP) {
+      T_hot = fmax(p->chem[3], p->inlet_T);
+      rho_ratio = T_hot / p->T_ref;
+    } else {
+      const double *ch = p->chem;
+      double Y[6], ys = 0.0;
+      for (int k = 0; k < 5; ++k) {
+        Y[k] = fmax(p->inlet_Y[k], 0.0);
+        ys += Y[k];
+      }
+      Y[5] = 1.0 - ys;
+      // CH4 + 2 O2 -> CO2 + 2 H2O, limited by fuel or oxygen (mol per kg)
+      const double xi = fmin(Y[0] / ch[5], 0.5 * Y[1] / ch[6]);
+      const double q = xi * (ch[11] + 2.0 * ch[12] - ch[14] - 2.0 * ch[15]);   // J/kg
+      T_hot = fmax(p->inlet_T, p->T_ref) + fmax(q, 0.0) / ch[4];
+      double Yb[6];
+      for (int k = 0; k < 6; ++k) Yb[k] = Y[k];
+      Yb[0] -= xi * ch[5];
+      Yb[1] -= 2.0 * xi * ch[6];
+      Yb[3] += xi * ch[8];
+      Yb[4] += 2.0 * xi * ch[9];
+      double invW = 0.0;
+      for (int k = 0; k < 6; ++k) invW += Yb[k] / ch[5 + k];
+      rho_ratio = (T_hot / p->T_ref) * (invW * ch[17]);        // rho_ref/rho = (T/T_ref)(W_ref/W)
+    }
+    double FD_hot = 0.0;
+    if (p->transport_model == LBM_TRANSPORT_MIXTURE) {
+      const double th = T_hot / p->T_ref;
+      double D0max = 0.0;
+      for (int k = 0; k < 15; ++k) D0max = fmax(D0max, p->transport[k]);
+      FD_hot = p->thickening * fmax(D0max * pow(th, p->transport[28]),
+                                    p->nu_ref * pow(th, p->transport[27]) * rho_ratio / p->prandtl);
+    } else {
+      FD_hot = p->thickening * p->nu_ref * rho_ratio / p->prandtl;
+    }
+    if (FD_hot > 1.0 / (2.0 * Dm)) {
+      snprintf(buf, sizeof buf,
+               "explicit diffusion unstable in the hottest gas (T = %g): F D = %g > 1/(2d) = %g", T_hot, FD_hot,
+               1.0 / (2.0 * Dm));
+      err = buf;
+      return LBM_E_INVALID;
+    }
+  }
   const int Dm = p->lattice == LBM_D2Q9 ? 2 : 3;
   for (int f = 0; f < 6; ++f)
     if (p->face_bc[f] < LBM_PERIODIC || p->face_bc[f] > LBM_OUTLET) return fail("unknown face condition");

@@ -43,6 +43,8 @@ def test_exports_every_declared_symbol():
     ({"nx": 0}, ">= 1"),
     ({"galilean": 1, "collision": "bgk"}, "cumulant"),
     ({"fourth_order": 1}, "D3Q27"),
+    ({"physics": "one_step", "visc_law": "const_mu", "nu_ref": 0.02, "thickening": 4.0,
+      "chem": [4.0, 15000.0, 300.0, 2000.0, 1.0]}, "hottest gas"),
     ({"fourth_order": 1, "lattice": "D3Q27", "nz": 4, "nu_ref": 1.0 / 18.0}, "stable range"),
     ({"fourth_order": 1, "lattice": "D3Q27", "nz": 4, "nu_ref": 1.0 / 6.0, "omega_bulk": 1.0}, "stable range"),
 ])

@@ -111,7 +111,7 @@ def test_fp32_rollout_against_finite_differences():
     J.backward()
     gu, gT = u0.grad.detach(), T0.grad.detach()
     rng = np.random.default_rng(1)
-    for _ in range(4):
+    for _ in range(16):                 # 16 random directions
         du = torch.from_numpy(rng.standard_normal(u.shape)).cuda()
         dT = torch.from_numpy(rng.standard_normal(T[0].shape)).cuda()
         ad = float((gu * du).sum() + (gT * dT).sum())
@@ -120,6 +120,8 @@ def test_fp32_rollout_against_finite_differences():
             Jp = float(rollout_objective(s, u0.detach() + eps * du, T0.detach() + eps * dT, Pd, K, 20))
             Jm = float(rollout_objective(s, u0.detach() - eps * du, T0.detach() - eps * dT, Pd, K, 20))
         fd = (Jp - Jm) / (2 * eps)
+        # FP32 rollouts: the central difference carries their rounding over 2 eps (one of 16
+        # directions measured 1.2 %)
         assert abs(fd - ad) <= 2e-2 * abs(fd), (fd, ad)
     s.close()
 
@@ -190,7 +192,7 @@ def test_full_size_fp32_rollout_finite_differences():
     gu, gT = u0.grad.detach(), T0.grad.detach()
     rng = np.random.default_rng(3)
     errs = []
-    for _ in range(4):
+    for _ in range(16):                 # 16 random directions
         du = torch.from_numpy(rng.standard_normal(u.shape)).cuda()
         dT = torch.from_numpy(rng.standard_normal(T[0].shape)).cuda()
         ad = float((gu * du).sum() + (gT * dT).sum())
@@ -201,5 +203,5 @@ def test_full_size_fp32_rollout_finite_differences():
         fd = (Jp - Jm) / (2 * eps)
         errs.append(abs(fd - ad) / abs(fd))
     print("128^3 x 2000 FD relative errors:", ["%.2e" % e for e in errs])
-    assert max(errs) <= 2e-2, errs
+    assert max(errs) <= 1e-2, errs
     s.close()
