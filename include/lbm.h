@@ -162,10 +162,13 @@ lbm_status lbm_query_sizes(const lbm_params *p, size_t *pop_bytes, size_t *scal_
                            size_t *work_bytes);
 
 /* Validates parameters (tau0 > 1/2, F D <= 1/(2 d) Fourier limit of the explicit
- * diffusion at rho_ref and, with rho nu constant or mixture transport, in the hottest gas
- * the chemistry can make (T_ad of the one-step model; the inlet mixture burnt completely
- * to CO2 and H2O for the two-step one), nz == 1 for D2Q9, sizes > 0, 0 <= omegas <= 2; a
- * closed domain has no inlet or outlet face and gamma > 1) and binds the buffers.  stream is a
+ * diffusion at rho_ref, nz == 1 for D2Q9, sizes > 0, 0 <= omegas <= 2; a closed domain has
+ * no inlet or outlet face and gamma > 1) and binds the buffers.  With rho nu constant or
+ * mixture transport the same limit is also estimated in the hottest gas the chemistry can
+ * make (T_ad of the one-step model; the inlet mixture burnt completely to CO2 and H2O for
+ * the two-step one); beyond it lbm_create (and lbm_query_sizes) still succeed but leave a
+ * message starting "warning:" in lbm_last_error (of the solver; of NULL for
+ * lbm_query_sizes), since runs that never get that hot are valid.  stream is a
  * hipStream_t (NULL = default stream).  scal_a/scal_b may be NULL when S == 0.
  * Builds the list of boundary cells (cells within two of a non-periodic face) for a
  * split step; synchronises the stream. */

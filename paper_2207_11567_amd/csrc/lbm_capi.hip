@@ -85,7 +85,8 @@ struct Layout {
       work_bytes;
 };
 
-static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
+static lbm_status validate(const lbm_params *p, Layout *L, std::string &err, std::string *warn_out = nullptr) {
+  std::string warn;
   char buf[256];
   auto fail = [&](const char *m) { err = m; return LBM_E_INVALID; };
   if (!p) return fail("params is NULL");
@@ -190,11 +191,11 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
       FD_hot = p->thickening * p->nu_ref * rho_ratio / p->prandtl;
     }
     if (FD_hot > 1.0 / (2.0 * Dm)) {
+      // a warning, not an error: short runs and states that never get this hot are valid
       snprintf(buf, sizeof buf,
-               "explicit diffusion unstable in the hottest gas (T = %g): F D = %g > 1/(2d) = %g", T_hot, FD_hot,
-               1.0 / (2.0 * Dm));
-      err = buf;
-      return LBM_E_INVALID;
+               "warning: explicit diffusion unstable in the hottest gas the chemistry can make (T = %g): "
+               "F D = %g > 1/(2d) = %g", T_hot, FD_hot, 1.0 / (2.0 * Dm));
+      warn = buf;
     }
   }
   const int Dm = p->lattice == LBM_D2Q9 ? 2 : 3;
@@ -245,6 +246,7 @@ static lbm_status validate(const lbm_params *p, Layout *L, std::string &err) {
   L->off_geom = align256(L->off_partials + (size_t)nrec * NSUM * sizeof(double));
   L->off_cells = align256(L->off_geom + (size_t)N * (Q == 9 ? 4 : 8));
   L->work_bytes = align256(L->off_cells + (size_t)N * sizeof(int));
+  if (warn_out) *warn_out = warn;
   return LBM_OK;
 }
 
@@ -498,8 +500,10 @@ extern "C" {
 
 lbm_status lbm_query_sizes(const lbm_params *p, size_t *pop_bytes, size_t *scal_bytes, size_t *work_bytes) {
   Layout L;
-  lbm_status st = validate(p, &L, g_create_err);
+  std::string warn;
+  lbm_status st = validate(p, &L, g_create_err, &warn);
   if (st != LBM_OK) return st;
+  g_create_err = warn;
   if (pop_bytes) *pop_bytes = L.pop_bytes;
   if (scal_bytes) *scal_bytes = L.scal_bytes;
   if (work_bytes) *work_bytes = L.work_bytes;
@@ -511,7 +515,8 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
   if (!out) return LBM_E_INVALID;
   *out = nullptr;
   Layout L;
-  lbm_status st = validate(p, &L, g_create_err);
+  std::string warn;
+  lbm_status st = validate(p, &L, g_create_err, &warn);
   if (st != LBM_OK) return st;
   if (!pop_a || !pop_b || !work || pop_a == pop_b) {
     g_create_err = "pop_a, pop_b (distinct) and work are required";
@@ -567,6 +572,7 @@ lbm_status lbm_create(const lbm_params *p, void *stream, void *pop_a, void *pop_
     delete s;
     return LBM_E_HIP;
   }
+  s->err = warn;                  // empty, or the warning of the parameter check
   *out = s;
   return LBM_OK;
 }

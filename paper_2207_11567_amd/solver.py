@@ -49,6 +49,10 @@ class Solver:
                                _ptr(self.work), ctypes.byref(h)))
         self._h = h
         self._mask = None
+        msg = lib.lbm_last_error(h)
+        if msg and msg.startswith(b"warning:"):
+            import warnings
+            warnings.warn(msg.decode(), RuntimeWarning, stacklevel=2)
 
     # ---------------------------------------------------------------- lifecycle
     def close(self):
