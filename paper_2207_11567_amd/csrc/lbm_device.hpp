@@ -55,6 +55,21 @@ enum : int { ST_FLUID = 0, ST_SOLID = 1, ST_INLET = 2, ST_OUTLET = 3 };
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
+// Exponential, base-2 logarithm and square root: the library's in FP64; in FP32 the
+// hardware's base-2 exponential, logarithm and square root (about 1 ulp for normal
+// arguments) without the library's range reduction and denormal scaling, which cost about
+// fifteen instructions each.  Their arguments here (temperature ratios, Arrhenius exponents
+// above -90, non-negative rates and concentrations) are normal or zero, and results that
+// would be denormal are physically zero.
+__device__ __forceinline__ double hexp(double x) { return exp(x); }
+__device__ __forceinline__ float hexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ double hexp2(double x) { return exp2(x); }
+__device__ __forceinline__ float hexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double hlog2(double x) { return log2(x); }
+__device__ __forceinline__ float hlog2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ double hsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // ------------------------------------------------------------------------ 1-D chimera
 // Central moments of orders 0,1,2 about u of a 3-point distribution on {-1,0,+1}
 // (Geier et al. 2015, the 1-D factor of the D2Q9/D3Q27 moment transform), in place.
@@ -107,8 +122,8 @@ template <class R>
 __device__ __forceinline__ R shear_rate(const Rates<R> &r, R PiPi) {
   // tau = (tau0 + sqrt(tau0^2 + 2 Cs^2 Qbar / cs2^2)) / 2, Qbar = sqrt(2 Pi:Pi)
   if (r.smag18 == R(0)) return fdiv(R(1), r.tau0);
-  const R Qbar = sqrt(R(2) * PiPi);
-  const R tau = R(0.5) * (r.tau0 + sqrt(r.tau0 * r.tau0 + r.smag18 * Qbar));
+  const R Qbar = hsqrt(R(2) * PiPi);
+  const R tau = R(0.5) * (r.tau0 + hsqrt(r.tau0 * r.tau0 + r.smag18 * Qbar));
   return fdiv(R(1), tau);
 }
 
@@ -428,9 +443,9 @@ __device__ __forceinline__ void mix_point(const MixT<R> &m, const ThermoT<R> &th
 #pragma unroll
   for (int k = 0; k < 6; ++k) o.X[k] = o.Y[k] * W * th.inv_W[k];
   const R T = v[0];
-  const R lt = log(T * m.inv_Tref);
-  mu = th.mu_ref * exp(m.s_mu * lt);
-  const R scale = fdiv(exp(m.s_D * lt), pi);
+  const R lt = hlog2(T * m.inv_Tref);       // (T/T_ref)^s = 2^(s log2(T/T_ref))
+  mu = th.mu_ref * hexp2(m.s_mu * lt);
+  const R scale = fdiv(hexp2(m.s_D * lt), pi);
   cp = R(0);
 #pragma unroll
   for (int k = 0; k < 6; ++k) cp += o.Y[k] * (m.cpa[k] + m.cpb[k] * T);

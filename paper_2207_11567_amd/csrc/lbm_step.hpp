@@ -800,7 +800,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         // chemistry (reaction over F) and Lambda (Eq. 3)
         const R invF = a.th.invF;
         if constexpr (NS == 2) {
-          const R r = a.th.B1 * fmax(phi0[1], R(0)) * exp(-fdiv(a.th.Ta1, phi0[0]));
+          const R r = a.th.B1 * fmax(phi0[1], R(0)) * hexp(-fdiv(a.th.Ta1, phi0[0]));
           R_s[0] += a.th.heat1 * r * invF;
           R_s[1] -= r * invF;
           if (a.thermo) R_s[0] += a.kap * qn * phi0[0];   // pressure work
@@ -812,8 +812,8 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
           for (int q = 0; q < 5; ++q) conc[q] = rho0 * fmax(phi0[1 + q], R(0)) * a.th.inv_W[q];
           const R T = phi0[0];
           const R iT = fdiv(R(1), T);
-          const R q1 = a.th.B1 * exp(-a.th.Ta1 * iT) * conc[0] * conc[1];
-          const R q2 = a.th.B2 * exp(-a.th.Ta2 * iT) * conc[2] * sqrt(conc[1]);
+          const R q1 = a.th.B1 * hexp(-a.th.Ta1 * iT) * conc[0] * conc[1];
+          const R q2 = a.th.B2 * hexp(-a.th.Ta2 * iT) * conc[2] * hsqrt(conc[1]);
           const R ir = irho0;
           // molar rates per mass: sum over reactions of nu_k,r q_r, over rho
           const R m0 = -q1 * ir, m1 = (R(-1.5) * q1 - R(0.5) * q2) * ir, m2 = (q1 - q2) * ir,

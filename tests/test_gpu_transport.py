@@ -53,19 +53,31 @@ def test_mixture_parity_fp64(lat, shape, faces):
     assert (np.abs(g_scal - st["scal"].numpy())[:, fl] / scale).max() < 1e-12
 
 
-@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 13, 70)), ("D3Q27", (7, 6, 9))])
-def test_mixture_parity_fp32(lat, shape):
-    p = _params(lat, shape, prec="fp32")
+@pytest.mark.parametrize("lat,shape,faces,solids", [
+    ("D2Q9", (1, 13, 70), None, False),
+    ("D3Q27", (7, 6, 9), None, False),
+    # 64x4 tiles (FP32 arithmetic): the transport points of a tile and its x/y halo are
+    # formed once and shared through LDS; halos wrap (periodic x, y) or stop at walls
+    ("D3Q27", (6, 8, 64), ["periodic", "periodic", "wall", "wall", "inlet", "outlet"], True),
+    ("D3Q27", (4, 8, 128), ["periodic", "periodic", "periodic", "periodic", "wall", "wall"], False),
+])
+def test_mixture_parity_fp32(lat, shape, faces, solids):
+    p = _params(lat, shape, prec="fp32", faces=faces)
     ghat, scal = random_state(p, 43)
+    solid = np.random.default_rng(3).uniform(size=shape) < 0.06 if solids else np.zeros(shape, bool)
     s = make_solver(p)
+    if solids:
+        s.set_geometry(torch.from_numpy(solid.astype(np.uint8)))
     gpu_state(s, ghat, scal)
     s.step(1)
     g_pops, g_scal, _ = fetch(s)
     s.close()
-    st, _ = OS.step(p, oracle_state(p, ghat, scal))
-    assert np.abs(g_pops - oracle_ghat(p, st)).max() < 2e-7
-    o = st["scal"].numpy()
-    scale = np.maximum(np.array(p["weno_scale"][:6]).reshape(-1, 1, 1, 1), np.abs(o))
+    st, _ = OS.step(p, oracle_state(p, ghat, scal, solid if solids else None))
+    fl = ~solid
+    g_pops, g_scal = g_pops[:, fl], g_scal[:, fl]
+    assert np.abs(g_pops - oracle_ghat(p, st)[:, fl]).max() < 2e-7
+    o = st["scal"].numpy()[:, fl]
+    scale = np.maximum(np.array(p["weno_scale"][:6]).reshape(-1, 1), np.abs(o))
     assert (np.abs(g_scal - o) / scale).max() < 2e-6
 
 
