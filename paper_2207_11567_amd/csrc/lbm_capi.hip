@@ -666,7 +666,7 @@ lbm_status lbm_step(lbm_solver *s, int32_t nsteps) {
     hipError_t e = launch_step_pass(s, a);
     if (e != hipSuccess) return hip_fail(s, e, "step kernel");
     if (s->closed) {
-      e = launch_finalize(s->partials, s->nrec, s->stage, s->sums, s->stream, s->thermo);
+      e = launch_thermo(s->partials, s->nrec, s->thermo, s->stream);
       if (e != hipSuccess) return hip_fail(s, e, "thermodynamic pressure update");
     }
     s->cur ^= 1;

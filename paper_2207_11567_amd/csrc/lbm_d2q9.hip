@@ -44,6 +44,11 @@ hipError_t launch_finalize(const double *partials, int nblocks, double *stage, d
   return hipGetLastError();
 }
 
+hipError_t launch_thermo(const double *partials, int nrec, double *thermo, hipStream_t st) {
+  hipLaunchKernelGGL(thermo_kernel, dim3(1), dim3(1024), 0, st, partials, nrec, thermo);
+  return hipGetLastError();
+}
+
 hipError_t launch_surface(int Q, int prec, const StepArgs &a, int nblocks, hipStream_t st, double T_u, double T_b) {
   const KArgs<double> k = to_kargs<double>(a);
   const double inv = 1.0 / (T_b - T_u);

@@ -31,6 +31,8 @@ hipError_t launch_adjoint(int prec, int ns, int kind, const StepArgs &sa, int nb
 hipError_t launch_finalize(const double *partials, int nblocks, double *stage, double *out, hipStream_t st,
                            double *thermo = nullptr);
 hipError_t launch_set_thermo(double *thermo, double pi, double q, double K, hipStream_t st);
+// Closed domain: (pi, q, K) of the next level from the step's nrec block records.
+hipError_t launch_thermo(const double *partials, int nrec, double *thermo, hipStream_t st);
 // Observables: flame-surface block records (slot 0 of the partials) and mean / RMS fields.
 hipError_t launch_surface(int Q, int prec, const StepArgs &a, int nblocks, hipStream_t st, double T_u, double T_b);
 hipError_t launch_statistics(const double *acc, int D, long long N, long long k, double P0, double *mean, double *rms,
