@@ -247,6 +247,18 @@ __device__ __forceinline__ void axis_offsets(int c, int n, int flo, int fhi, int
       off[k] = (k - 2) * stride;
       code[k] = -1;
     }
+  } else if (flo < 0 && fhi < 0) {
+    // periodic axis: the wrap alone, by selects (twice, for extents of one cell)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      int p = c + k - 2;
+      p += p < 0 ? n : 0;
+      p -= p >= n ? n : 0;
+      p += p < 0 ? n : 0;
+      p -= p >= n ? n : 0;
+      off[k] = (p - c) * stride;
+      code[k] = -1;
+    }
   } else {
     const AxisNb A = axis_nb(c, n, flo, fhi);
 #pragma unroll
