@@ -417,13 +417,28 @@ def main():
         return
     if args.copy_calib:
         import torch
+        from paper_2207_11567_amd.solver import copy_probe
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
-        torch.cuda.synchronize()
+        # the same bytes through the step kernel's own load and store forms (library copy
+        # probe, modes 0-3: cached / streaming loads x cached / streaming stores), timed
+        gbs = {}
+        for mode in range(4):
+            copy_probe(a, b, mode)                        # first launch of this form: untimed
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                copy_probe(a, b, mode)
+            e1.record()
+            torch.cuda.synchronize()
+            gbs[mode] = round(3 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
+        if not torch.equal(a, b):
+            raise RuntimeError("copy probe: destination differs from source")
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4,
-                          "launches": 3}))
+                          "launches": 3, "probe_gbs_by_mode": gbs}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the time step is measured on one "

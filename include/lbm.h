@@ -317,6 +317,19 @@ lbm_status lbm_objective(lbm_solver *s, const void *state_pops, const void *stat
 lbm_status lbm_init_adjoint(lbm_solver *s, const void *adj_pop, const void *adj_scal,
                             const double *u0, double *grad_u, double *grad_scal);
 
+/* Measurement support, not part of the method: copies `bytes` (0 < bytes <= 2^31, a
+ * multiple of 4) from src to dst (device pointers of the current device, not overlapping)
+ * with the 4-byte raw buffer loads and stores that the step kernel uses, one element per
+ * lane and 64 consecutive ones per wave.  mode bit 0: streaming (non-temporal) loads, else
+ * cached ones (the step's scalar loads and its pull loads on large grids); bit 1: streaming
+ * stores (the step's population stores), else cached ones (its scalar stores).  For
+ * calibrating the memory counters (FETCH_SIZE, WRITE_SIZE) of exactly these forms against a
+ * known byte count, and for the bandwidth they reach.  Asynchronous on `stream` (a
+ * hipStream_t, NULL for the default stream); the caller keeps both buffers alive until the
+ * stream has passed the copy.  LBM_E_INVALID for a bad size, mode or pointer (message in
+ * lbm_last_error(NULL)), LBM_E_HIP if the launch fails. */
+lbm_status lbm_copy_probe(const void *src, void *dst, size_t bytes, int32_t mode, void *stream);
+
 /* Human-readable message of the last failure on this solver. */
 const char *lbm_last_error(const lbm_solver *s);
 

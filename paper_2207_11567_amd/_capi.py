@@ -103,6 +103,7 @@ def _load():
         "lbm_flame_surface": [c_void_p, c_double, c_double, P(c_double)],
         "lbm_flame_surface_noalloc": [c_void_p, c_double, c_double, c_void_p],
         "lbm_set_thermo_pressure": [c_void_p, P(c_double)],
+        "lbm_copy_probe": [c_void_p, c_void_p, ctypes.c_size_t, c_int32, c_void_p],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -496,6 +497,27 @@ static __global__ void copy_first_kernel(const double *src, double *dst) {
   if (threadIdx.x == 0) dst[0] = src[0];
 }
 
+// Device copy through the step's own memory forms: 4-byte raw buffer loads (streaming when
+// bit 0 of MODE is set, else cached) and 4-byte raw buffer stores (streaming when bit 1 is
+// set), one element per lane and 64 consecutive ones per wave, eight loads in flight per
+// lane.  n < 2^29 elements, so every byte offset fits the 32-bit buffer offset.
+template <int MODE>
+__global__ __launch_bounds__(256) void copy_probe_kernel(const float *src, float *dst, unsigned n) {
+  constexpr int LA = (MODE & 1) ? 2 : 0, SA = (MODE & 2) ? 2 : 0;
+  const auto rs = slice(src);
+  const auto rd = slice(dst);
+  const unsigned stride = gridDim.x * 256u;
+  unsigned i = blockIdx.x * 256u + threadIdx.x;
+  for (; i + 7u * stride < n; i += 8u * stride) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = bld<float, LA>(rs, i + (unsigned)j * stride);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bst<float, SA>(rd, i + (unsigned)j * stride, v[j]);
+  }
+  for (; i < n; i += stride) bst<float, SA>(rd, i, bld<float, LA>(rs, i));
+}
+
 extern "C" {
 
 lbm_status lbm_query_sizes(const lbm_params *p, size_t *pop_bytes, size_t *scal_bytes, size_t *work_bytes) {
@@ -878,6 +900,36 @@ lbm_status lbm_flame_surface_noalloc(lbm_solver *s, double T_u, double T_b, doub
     e = hipGetLastError();
   }
   if (e != hipSuccess) return hip_fail(s, e, "flame surface (no allocation)");
+  return LBM_OK;
+}
+
+lbm_status lbm_copy_probe(const void *src, void *dst, size_t bytes, int32_t mode, void *stream) {
+  if (!src || !dst || bytes == 0 || bytes % 4 != 0 || bytes > ((size_t)1 << 31) || mode < 0 || mode > 3) {
+    g_create_err = "lbm_copy_probe: device pointers, 0 < bytes <= 2^31 and a multiple of 4, mode 0..3 are required";
+    return LBM_E_INVALID;
+  }
+  const char *a = (const char *)src, *b = (const char *)dst;
+  if (a < b + bytes && b < a + bytes) {
+    g_create_err = "lbm_copy_probe: source and destination overlap";
+    return LBM_E_INVALID;
+  }
+  const unsigned n = (unsigned)(bytes / 4);
+  const unsigned blocks = std::min<unsigned>((n + 255u) / 256u, 8192u);
+  hipStream_t st = (hipStream_t)stream;
+  const float *fs = (const float *)src;
+  float *fd = (float *)dst;
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(copy_probe_kernel<0>, dim3(blocks), dim3(256), 0, st, fs, fd, n); break;
+    case 1: hipLaunchKernelGGL(copy_probe_kernel<1>, dim3(blocks), dim3(256), 0, st, fs, fd, n); break;
+    case 2: hipLaunchKernelGGL(copy_probe_kernel<2>, dim3(blocks), dim3(256), 0, st, fs, fd, n); break;
+    default: hipLaunchKernelGGL(copy_probe_kernel<3>, dim3(blocks), dim3(256), 0, st, fs, fd, n); break;
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_create_err = std::string("lbm_copy_probe: ") + hipGetErrorString(e);
+    return LBM_E_HIP;
+  }
+  g_create_err.clear();
   return LBM_OK;
 }
 

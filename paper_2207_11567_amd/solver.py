@@ -14,6 +14,22 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def copy_probe(src, dst, mode, stream=None):
+    """lbm_copy_probe: copy the bytes of contiguous device tensor src into dst with the step
+    kernel's raw buffer loads (mode bit 0: streaming) and stores (bit 1: streaming), on
+    `stream` (torch's current stream by default); measurement support."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("copy_probe: contiguous device tensors are required")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy_probe: source and destination sizes differ")
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    lib = C.lib()
+    status = lib.lbm_copy_probe(_ptr(src), _ptr(dst), nbytes, int(mode), ctypes.c_void_p(st.cuda_stream))
+    if status != 0:
+        raise C.LbmError(status, lib.lbm_last_error(None).decode())
+
+
 class Solver:
     """One lattice (D2Q9 or D3Q27) with its A/B population and scalar buffers on a GPU."""
 

@@ -88,3 +88,15 @@ def test_hot_gas_diffusion_limit_warns():
     p["nu_ref"] = 0.002
     assert lib.lbm_query_sizes(ctypes.byref(C.make_params(p)), None, None, None) == C.LBM_OK
     assert lib.lbm_last_error(None).decode() == ""
+
+
+def test_copy_probe_rejects_bad_arguments():
+    """Host-side checks of lbm_copy_probe (no copy is launched): size, mode, null and
+    overlapping pointers."""
+    C, lib = _lib()
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
+    for src, dst, nbytes, mode in [(a, b, 6, 0), (a, b, 0, 0), (a, b, (1 << 31) + 4, 0), (a, b, 64, 4),
+                                   (a, b, 64, -1), (None, b, 64, 0), (a, None, 64, 0),
+                                   (a, ctypes.c_void_p((1 << 20) + 32), 64, 0)]:
+        assert lib.lbm_copy_probe(src, dst, nbytes, mode, None) == C.LBM_E_INVALID
+        assert lib.lbm_last_error(None).decode().startswith("lbm_copy_probe:")
