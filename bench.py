@@ -398,8 +398,8 @@ def differentiation(nsteps=2000, seg=100, n=128):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--repeats", type=int, default=3,
                     help="timed regions of --steps steps each; ms_per_step is their median")
     ap.add_argument("--workload", default="reacting_box",
