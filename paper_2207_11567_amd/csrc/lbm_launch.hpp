@@ -86,7 +86,12 @@ hipError_t launch_one(int kind, const StepArgs &a, int nblocks, hipStream_t st, 
     case LAUNCH_STEP:
       return full ? launch_step<Q, PREC, NS, true, MODE_ALL>(a, nblocks, st)
                   : launch_step<Q, PREC, NS, false, MODE_ALL>(a, nblocks, st);
-    case LAUNCH_STEP_INTERIOR: return a.mix ? launch_step<Q, PREC, NS, true, MODE_INTERIOR>(a, nblocks, st) : launch_step<Q, PREC, NS, false, MODE_INTERIOR>(a, nblocks, st);
+    case LAUNCH_STEP_INTERIOR:   // on the 64x4 tile grid when it fits, else on linear tiles
+      if (a.band_rows)
+        return a.mix ? launch_step<Q, PREC, NS, true, MODE_INTERIOR>(a, nblocks, st)
+                     : launch_step<Q, PREC, NS, false, MODE_INTERIOR>(a, nblocks, st);
+      return a.mix ? launch_step<Q, PREC, NS, true, MODE_INTERIOR_LIN>(a, nblocks, st)
+                   : launch_step<Q, PREC, NS, false, MODE_INTERIOR_LIN>(a, nblocks, st);
     case LAUNCH_STEP_LIST:
       return (a.lvl || a.mix) ? launch_step<Q, PREC, NS, true, MODE_LIST>(a, nblocks, st)
                    : launch_step<Q, PREC, NS, false, MODE_LIST>(a, nblocks, st);

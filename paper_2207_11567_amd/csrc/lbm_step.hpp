@@ -30,10 +30,12 @@ namespace lbm {
 constexpr int NSUM = 9;
 // collision operator compiled into a step instance
 enum : int { COLL_CUM1 = 0, COLL_CUM = 1, COLL_BGK = 2 };
-// cells a step instance updates: every cell (tile grid), the interior cells only (tile grid;
-// the code of boundaries, solids and curved walls is not compiled in), or the cells of a
-// list (one thread per listed cell: the cells the interior instance leaves)
-enum : int { MODE_ALL = 0, MODE_INTERIOR = 1, MODE_LIST = 2 };
+// cells a step instance updates: every cell (64x4 tile grid when it fits, else linear
+// 256-cell tiles), the interior cells only (the code of boundaries, solids and curved walls
+// is not compiled in; on the tile grid, where a wave's y and z are scalars, or on linear
+// tiles for grids the tiles do not fit), or the cells of a list (one thread per listed
+// cell: the cells the interior instance leaves)
+enum : int { MODE_ALL = 0, MODE_INTERIOR = 1, MODE_LIST = 2, MODE_INTERIOR_LIN = 3 };
 
 // Host-side description of one launch (double precision constants).
 struct Thermo {
@@ -375,7 +377,7 @@ __device__ __forceinline__ double w_over_T(const ThermoT<R> &t, const R (&v)[NS 
 template <int Q, int PREC, int NS, bool EXTRACT, bool FULL, int COLL, int MODE>
 constexpr int step_waves_per_eu() {
   return (Q == 27 && PREC != 0 && NS == 6 && !EXTRACT && COLL == COLL_CUM1 && MODE != MODE_LIST &&
-          (!FULL || MODE == MODE_INTERIOR))
+          (!FULL || MODE == MODE_INTERIOR || MODE == MODE_INTERIOR_LIN))
              ? 4
              : 1;
 }
@@ -391,12 +393,16 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
   constexpr int D = Lat<Q>::D;
   constexpr int NSV = NS > 0 ? NS : 1;
   constexpr R s = R(1.0 / 3.0);
+  constexpr bool INTER = MODE == MODE_INTERIOR || MODE == MODE_INTERIOR_LIN;   // interior cells only
+  // the plain interior instance takes y and z as scalars (the FULL one keeps them per lane:
+  // as scalars its register pressure spills more)
+  constexpr bool UNIYZ = MODE == MODE_INTERIOR && !FULL;
 
   // Interior instance: the wave runs at a raised priority until its populations and cell
   // scalars are loaded and the velocity is formed, so that waves about to issue loads
   // are not starved by waves deep in their arithmetic (reacting box 0.869 -> 0.860 ms;
   // keeping it raised through the scalar stencils too was slower, 0.883 ms).
-  if constexpr (MODE == MODE_INTERIOR) __builtin_amdgcn_s_setprio(2);
+  if constexpr (INTER) __builtin_amdgcn_s_setprio(2);
   const int tile = tile_of_block(blockIdx.x, gridDim.x, a.remap);
   // Banded tile order: 64x4-cell tiles, visited band of rows by band, and inside a band
   // plane by plane, so the +-1 and +-2 planes of the scalar stencils were touched a few
@@ -412,7 +418,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
     const int rem = n - z * nxy;
     y = rem / a.nx;
     x = rem - y * a.nx;
-  } else if (a.band_rows) {
+  } else if (MODE == MODE_INTERIOR || (MODE == MODE_ALL && a.band_rows)) {
     const int nxt = a.nx >> 6, bt = a.band_rows >> 2;
     const int per_plane = nxt * bt, per_band = per_plane * a.nz;
     const int band = tile / per_band, r = tile - band * per_band;
@@ -421,6 +427,12 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
     x = (xt << 6) + ((int)threadIdx.x & 63);
     y = band * a.band_rows + (ys << 2) + ((int)threadIdx.x >> 6);
     z = zz;
+    if constexpr (UNIYZ) {
+      // a wave is 64 cells of one row of one plane: y and z are the same in every lane,
+      // so their offsets are scalar values
+      y = __builtin_amdgcn_readfirstlane(y);
+      z = __builtin_amdgcn_readfirstlane(z);
+    }
     n = x + a.nx * (y + a.ny * z);
   } else {
     n = tile * (int)blockDim.x + (int)threadIdx.x;
@@ -440,12 +452,12 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
 
   bool active = listed && n < N;
   const GW gw = active && a.geom ? ((const GW *)a.geom)[n] : GW(0);
-  if constexpr (MODE == MODE_INTERIOR)
+  if constexpr (INTER)
     active = active && gw == GW(0) && !near_face(x, a.nx, a.face[0], a.face[1]) &&
              !near_face(y, a.ny, a.face[2], a.face[3]) && !near_face(z, a.nz, a.face[4], a.face[5]);
   if (active) {
     const int nxy = a.nx * a.ny;
-    if (MODE != MODE_INTERIOR && (gw & (GW(1) << bit_self<Q>()))) {
+    if (!INTER && (gw & (GW(1) << bit_self<Q>()))) {
       if (!EXTRACT) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) pout[i * N + n] = pin[i * N + n];
@@ -552,7 +564,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
       const bool border = code[0][1] >= 0 || code[0][3] >= 0 || code[1][1] >= 0 || code[1][3] >= 0 ||
                           (D == 3 && (code[2][1] >= 0 || code[2][3] >= 0));
       constexpr GW linkmask = (GW(1) << Q) - GW(1);
-      if (MODE == MODE_INTERIOR || (!border && !(gw & linkmask))) {
+      if (INTER || (!border && !(gw & linkmask))) {
         // PULLC (grids larger than the Infinity Cache): ordinary cached loads.  A wave's 64
         // shifted values of a population with c_x != 0 straddle a cache line that the
         // neighbouring tile in x reads too, and with streaming loads that line was often
@@ -562,10 +574,18 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
         constexpr int PULL_AUX = PULLC ? 0 : 2;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const unsigned m = un + (unsigned)(off[0][2 - cx(i)] + off[1][2 - cy(i)] + (D == 3 ? off[2][2 - cz(i)] : 0));
-          gh[i] = decode<R>(bld<St, PULL_AUX>(slice(pin + (size_t)i * N), m));
+          if constexpr (UNIYZ) {
+            // the wave-uniform y/z part of the offset moves the slice's base (scalar
+            // arithmetic); the lanes add only the x part (three distinct offsets)
+            const long long yz = (long long)off[1][2 - cy(i)] + (D == 3 ? off[2][2 - cz(i)] : 0);
+            const St *base = (const St *)((const char *)pin + ((long long)i * N + yz) * (long long)sizeof(St));
+            gh[i] = decode<R>(bld<St, PULL_AUX>(slice(base), un + (unsigned)off[0][2 - cx(i)]));
+          } else {
+            const unsigned m = un + (unsigned)(off[0][2 - cx(i)] + off[1][2 - cy(i)] + (D == 3 ? off[2][2 - cz(i)] : 0));
+            gh[i] = decode<R>(bld<St, PULL_AUX>(slice(pin + (size_t)i * N), m));
+          }
         }
-      } else if constexpr (MODE != MODE_INTERIOR) {
+      } else if constexpr (!INTER) {
         // boundary cell: bounce-back, moving-wall inlet, anti-bounce-back outlet
         R uw_in[3] = {R(a.inlet_u[0]), R(a.inlet_u[1]), R(a.inlet_u[2])};
         if (a.inlet_noise != 0.0) {
@@ -661,7 +681,7 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
       const R P0 = R(a.P0);
       const R mom = R(3) * P0 * irho0;           // rho u = P0 sum c ghat / cs2
       const R u[3] = {mx * mom, my * mom, D == 3 ? mz * mom : R(0)};
-      if constexpr (MODE == MODE_INTERIOR) __builtin_amdgcn_s_setprio(0);
+      if constexpr (INTER) __builtin_amdgcn_s_setprio(0);
 
       // ---------------------------------------------------------------- scalar stencils
       // One pass per axis: the five stencil values of every scalar (ghost rules at walls,
@@ -801,8 +821,8 @@ void step_kernel(KArgs<typename Prec<PREC>::R> a) {
             }
           }
         };
-        if (MODE == MODE_INTERIOR || interior) stencils(std::true_type{});
-        else if constexpr (MODE != MODE_INTERIOR) stencils(std::false_type{});
+        if (INTER || interior) stencils(std::true_type{});
+        else if constexpr (!INTER) stencils(std::false_type{});
         const R Fr = a.th.F * irho0;
 #pragma unroll
         for (int q = 0; q < NS; ++q) R_s[q] *= Fr;
