@@ -446,8 +446,8 @@ def main():
                           "launches": 3, "probe_gbs_by_mode": gbs}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the time step is measured on one "
-                                   "MI355X; multi-GPU sharding is a design note only",
+        print(json.dumps({"error": "the library steps one grid on one GPU: the time step is measured on one "
+                                   "MI355X; sharding across GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
