@@ -157,3 +157,44 @@ def test_chamber_full_size_mass_and_isentropic_compression():
     assert pi > 1.0 + 1e-4
     kappa = 0.4 / 1.4
     assert abs(T_far / 300.0 / pi ** kappa - 1) < 1e-4
+
+
+def test_closed_split_step_on_the_tile_grid_matches_the_small_box():
+    """A closed box periodic in x and y with walls in z, and the same box tiled 4 x 4 in x
+    and y: the tiled one (about a million cells) runs the split step on the 64x4 tile grid
+    (interior instance with a wave's y and z as scalars, list instance at the z walls, the
+    pi update over both halves' records), the small one the single all-cell instance.
+    Every cell sees the same neighbours and the sums scale by 16 exactly, so after 10 steps
+    the two agree to the rounding of the differently ordered sums: ghat to 1e-12, each
+    scalar to 1e-12 of its range, pi to 1e-13 and a pi that moved."""
+    from tests.gpu_helpers import fetch as _fetch
+    nz, ny, nx = 16, 64, 64
+    yf, yo, _ = L.fresh_ch4_air(0.83)
+    b = L.burnt_ch4_air(0.83)
+    base = L.base_params("D3Q27", nx, ny, nz, physics="two_step", visc_law="const_mu", nu_ref=0.02,
+                         cs_smag=0.17, prandtl=0.7, thickening=2.0, chem=L.two_step_chem(B1=50.0, B2=5.0),
+                         T_ref=320.0, weno_scale=[1630.0, 0.05, 0.22, 0.05, 0.13, 0.11, 1.0, 1.0],
+                         face_bc=["periodic"] * 4 + ["wall", "wall"], pth_mode="closed", gamma=1.4,
+                         precision="fp64")
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    c = 0.5 * (1 - np.tanh((z - nz / 2 + 2.0 * np.sin(2 * np.pi * x / nx) * np.cos(2 * np.pi * y / ny)) / 2.0))[None]
+    scal = np.concatenate([320.0 + 1630.0 * c, yf * (1 - c), yo * (1 - c) + b["O2"] * c, 0.0 * c,
+                           b["CO2"] * c, b["H2O"] * c])
+    P = np.full((nz, ny, nx), CS2)
+    u = np.zeros((3, nz, ny, nx))
+    out = []
+    for r in (1, 4):
+        p = dict(base, ny=r * ny, nx=r * nx)
+        print(f"closed tiled box {nz}x{p['ny']}x{p['nx']}", flush=True)
+        s = make_solver(p)
+        s.init_fields(torch.from_numpy(np.tile(P, (1, r, r))), torch.from_numpy(np.tile(u, (1, 1, r, r))),
+                      torch.from_numpy(np.tile(scal, (1, 1, r, r))))
+        s.step(10)
+        pops, sc, _ = _fetch(s)
+        out.append((pops, sc, s.thermo_pressure()))
+        s.close()
+    (p0, s0, t0), (p1, s1, t1) = out
+    assert np.abs(np.tile(p0, (1, 1, 4, 4)) - p1).max() < 1e-12
+    scale = np.array(base["weno_scale"][:6]).reshape(-1, 1, 1, 1)
+    assert (np.abs(np.tile(s0, (1, 1, 4, 4)) - s1) / scale).max() < 1e-12
+    assert abs(t1[0] / t0[0] - 1) < 1e-13 and t0[0] != 1.0

@@ -53,16 +53,21 @@ def test_mixture_parity_fp64(lat, shape, faces):
     assert (np.abs(g_scal - st["scal"].numpy())[:, fl] / scale).max() < 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
 @pytest.mark.parametrize("lat,shape,faces,solids", [
     ("D2Q9", (1, 13, 70), None, False),
     ("D3Q27", (7, 6, 9), None, False),
-    # 64x4 tiles (FP32 arithmetic): the transport points of a tile and its x/y halo are
-    # formed once and shared through LDS; halos wrap (periodic x, y) or stop at walls
+    # on the 64x4 tile grid: neighbour points across the x/y tile edges, wrapped (periodic
+    # x, y) or stopped at walls and solids
     ("D3Q27", (6, 8, 64), ["periodic", "periodic", "wall", "wall", "inlet", "outlet"], True),
     ("D3Q27", (4, 8, 128), ["periodic", "periodic", "periodic", "periodic", "wall", "wall"], False),
 ])
-def test_mixture_parity_fp32(lat, shape, faces, solids):
-    p = _params(lat, shape, prec="fp32", faces=faces)
+def test_mixture_parity_fp32(lat, shape, faces, solids, prec):
+    """FP32 arithmetic with FP32 or FP16 population storage against the FP64 oracle on
+    inputs rounded to the storage precision; the FP16-storage bound adds half an FP16 ulp of
+    the value (the output is rounded to half precision)."""
+    print(f"mixture parity {prec} {lat} {shape}", flush=True)
+    p = _params(lat, shape, prec=prec, faces=faces)
     ghat, scal = random_state(p, 43)
     solid = np.random.default_rng(3).uniform(size=shape) < 0.06 if solids else np.zeros(shape, bool)
     s = make_solver(p)
@@ -75,7 +80,9 @@ def test_mixture_parity_fp32(lat, shape, faces, solids):
     st, _ = OS.step(p, oracle_state(p, ghat, scal, solid if solids else None))
     fl = ~solid
     g_pops, g_scal = g_pops[:, fl], g_scal[:, fl]
-    assert np.abs(g_pops - oracle_ghat(p, st)[:, fl]).max() < 2e-7
+    o_pops = oracle_ghat(p, st)[:, fl]
+    tol = 2e-7 + (np.abs(o_pops) * 2.0 ** -11 if prec == "fp16s" else 0.0)
+    assert (np.abs(g_pops - o_pops) <= tol).all(), np.abs(g_pops - o_pops).max()
     o = st["scal"].numpy()[:, fl]
     scale = np.maximum(np.array(p["weno_scale"][:6]).reshape(-1, 1), np.abs(o))
     assert (np.abs(g_scal - o) / scale).max() < 2e-6
